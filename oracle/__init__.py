@@ -1,0 +1,234 @@
+"""ctypes wrapper of the FP64 C oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The library's product path never imports
+it.  See oracle.c for the readings of the paper that it implements.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+_lib = None
+
+I32P = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+F64P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+U32P = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+
+OR_M_IDENTITY, OR_M_GNP, OR_M_DENSE, OR_M_DIAG = 0, 1, 2, 3
+MGS, CGS2 = 0, 1
+
+
+class Precond(C.Structure):
+    _fields_ = [("kind", C.c_int),
+                ("rp", C.c_void_p), ("ci", C.c_void_p), ("ahat", C.c_void_p),
+                ("L", C.c_int), ("d", C.c_int), ("h", C.c_int),
+                ("theta", C.c_void_p), ("mat", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("mismatch", C.c_int), ("breakdowns", C.c_int),
+                ("rel_res_true", C.c_double), ("rel_res_est", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(
+                os.path.join(os.path.dirname(LIB), "oracle.c")):
+            build()
+        L = C.CDLL(LIB)
+        L.or_spmm.argtypes = [C.c_int64, I32P, I32P, F64P, C.c_int, F64P, F64P]
+        L.or_gamma.argtypes = [C.c_int64, I32P, I32P, F64P]
+        L.or_gamma.restype = C.c_double
+        L.or_scale.argtypes = [C.c_int64, F64P, C.c_double, F64P]
+        L.or_transpose.argtypes = [C.c_int64, I32P, I32P, F64P, I32P, I32P, F64P]
+        L.or_gnp_nparams.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.or_gnp_nparams.restype = C.c_int64
+        L.or_gnp_forward.argtypes = [C.c_int64, I32P, I32P, F64P, C.c_int, C.c_int, C.c_int,
+                                     F64P, C.c_int, F64P, F64P, C.c_void_p]
+        L.or_gnp_loss_grad.argtypes = [C.c_int64, I32P, I32P, F64P, F64P, C.c_int, C.c_int,
+                                       C.c_int, F64P, C.c_int, F64P, C.c_void_p, C.c_void_p]
+        L.or_gnp_loss_grad.restype = C.c_double
+        L.or_adam.argtypes = [C.c_int64, F64P, F64P, F64P, F64P, C.c_int, C.c_double,
+                              C.c_double, C.c_double, C.c_double]
+        L.or_philox4x32_10.argtypes = [U32P, U32P, U32P]
+        L.or_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64]
+        L.or_normal.restype = C.c_double
+        L.or_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, F64P]
+        L.or_train.argtypes = [C.c_int64, I32P, I32P, F64P, F64P, C.c_int, C.c_int, C.c_int,
+                               F64P, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                               C.c_double, C.c_uint64, C.c_void_p, C.c_void_p,
+                               C.POINTER(C.c_int)]
+        L.or_train.restype = C.c_int
+        L.or_fgmres.argtypes = [C.c_int64, I32P, I32P, F64P, C.POINTER(Precond), F64P, F64P,
+                                C.c_int, C.c_double, C.c_int, C.c_int, C.c_void_p,
+                                C.POINTER(Info), C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.POINTER(C.c_int)]
+        L.or_fgmres.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --- CSR ---------------------------------------------------------------------
+
+def spmm(A, x):
+    """y = A x; x of shape [n] or [n, B] (node-major)."""
+    x = _c64(x)
+    B = 1 if x.ndim == 1 else x.shape[1]
+    y = np.empty_like(x)
+    lib().or_spmm(A.n, A.rowptr, A.colind, _c64(A.val), B, x, y)
+    return y
+
+
+def gamma(A) -> float:
+    """Eq. (4)."""
+    return lib().or_gamma(A.n, A.rowptr, A.colind, _c64(A.val))
+
+
+def scale(val, s):
+    val = _c64(val)
+    out = np.empty_like(val)
+    lib().or_scale(val.size, val, float(s), out)
+    return out
+
+
+def transpose(A):
+    from paper_2406_00809_amd.inputs import CSR
+    trp = np.empty(A.n + 1, dtype=np.int32)
+    tci = np.empty(A.nnz, dtype=np.int32)
+    tv = np.empty(A.nnz, dtype=np.float64)
+    lib().or_transpose(A.n, A.rowptr, A.colind, _c64(A.val), trp, tci, tv)
+    return CSR(A.n, trp, tci, tv, A.name + "_T")
+
+
+class System:
+    """Oracle-side system: prescaled A (harness, Sec. 3) and A-hat (Eq. (4))."""
+
+    def __init__(self, A, prescale: bool = True):
+        from paper_2406_00809_amd.inputs import CSR
+        self.raw = A
+        g0 = gamma(A)
+        self.gamma_raw = g0
+        val = scale(A.val, g0) if prescale else _c64(A.val).copy()
+        self.A = CSR(A.n, A.rowptr, A.colind, val, A.name)
+        self.gamma = gamma(self.A)
+        self.ahat = scale(self.A.val, self.gamma)
+        self.n = A.n
+
+
+# --- network ---------------------------------------------------------------
+
+def nparams(L, d, h):
+    return int(lib().or_gnp_nparams(L, d, h))
+
+
+def gnp_forward(S: System, L, d, h, theta, b, return_acts=False):
+    """M(b), Sec. 2.3; b of shape [n] or [n, B]."""
+    b = _c64(b)
+    B = 1 if b.ndim == 1 else b.shape[1]
+    z = np.empty_like(b)
+    acts = np.empty((L + 1, S.n, B, d)) if return_acts else None
+    lib().or_gnp_forward(S.n, S.A.rowptr, S.A.colind, S.ahat, L, d, h, _c64(theta), B, b, z,
+                         _ptr(acts))
+    return (z, acts) if return_acts else z
+
+
+def loss_grad(S: System, L, d, h, theta, b, want_grad=True):
+    """Training loss mean|A M(b) - b| and its gradient (Sec. 3)."""
+    b = _c64(b)
+    B = 1 if b.ndim == 1 else b.shape[1]
+    g = np.empty(nparams(L, d, h)) if want_grad else None
+    loss = lib().or_gnp_loss_grad(S.n, S.A.rowptr, S.A.colind, _c64(S.A.val), S.ahat, L, d, h,
+                                  _c64(theta), B, b, _ptr(g), None)
+    return (loss, g) if want_grad else loss
+
+
+def adam(theta, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    lib().or_adam(theta.size, theta, _c64(g), m, v, t, lr, b1, b2, eps)
+
+
+def philox(ctr, key):
+    out = np.empty(4, dtype=np.uint32)
+    lib().or_philox4x32_10(np.asarray(ctr, dtype=np.uint32), np.asarray(key, dtype=np.uint32),
+                           out)
+    return out
+
+
+def normals(seed, step, count):
+    out = np.empty(count)
+    lib().or_normals(seed, step, count, out)
+    return out
+
+
+def train(S: System, L, d, h, theta0, steps, B, lr=1e-3, seed=2, x_fixed=None,
+          b1=0.9, b2=0.999, eps=1e-8):
+    theta = _c64(theta0).copy()
+    hist = np.empty(steps)
+    best = C.c_int(-1)
+    xf = None if x_fixed is None else _c64(x_fixed)
+    st = lib().or_train(S.n, S.A.rowptr, S.A.colind, _c64(S.A.val), S.ahat, L, d, h, theta,
+                        steps, B, lr, b1, b2, eps, seed, _ptr(xf), _ptr(hist), C.byref(best))
+    return theta, hist, best.value, st
+
+
+# --- FGMRES ------------------------------------------------------------------
+
+def fgmres(S: System, b, m, rtol, maxiters, M="identity", theta=None, arch=None, mat=None,
+           ortho=CGS2, x0=None, dump=False):
+    """Algorithm 1 with the stopping readings of oracle.c.
+
+    M: "identity" | "gnp" (theta, arch=(L,d,h)) | "dense" (mat n x n) | "diag" (mat n).
+    Returns dict with x, hist, info (and V, Z, H, k if dump).
+    """
+    n = S.n
+    b = _c64(b)
+    x = np.zeros(n) if x0 is None else _c64(x0).copy()
+    keep = []
+    pc = Precond()
+    if M == "identity":
+        pc.kind = OR_M_IDENTITY
+    elif M == "gnp":
+        pc.kind = OR_M_GNP
+        L, d, h = arch
+        th = _c64(theta)
+        keep += [th]
+        pc.rp, pc.ci, pc.ahat = (S.A.rowptr.ctypes.data, S.A.colind.ctypes.data,
+                                 S.ahat.ctypes.data)
+        pc.L, pc.d, pc.h, pc.theta = L, d, h, th.ctypes.data
+    elif M in ("dense", "diag"):
+        pc.kind = OR_M_DENSE if M == "dense" else OR_M_DIAG
+        mm = _c64(mat)
+        keep += [mm]
+        pc.mat = mm.ctypes.data
+    else:
+        raise ValueError(M)
+    hist = np.full(maxiters + 1, np.nan)
+    info = Info()
+    V = np.zeros((m + 1, n)) if dump else None
+    Z = np.zeros((m, n)) if dump else None
+    H = np.zeros((m + 1, m)) if dump else None
+    k = C.c_int(0)
+    lib().or_fgmres(n, S.A.rowptr, S.A.colind, _c64(S.A.val), C.byref(pc), b, x, m, rtol,
+                    maxiters, ortho, _ptr(hist), C.byref(info), _ptr(V), _ptr(Z), _ptr(H),
+                    C.byref(k))
+    out = dict(x=x, hist=hist[: info.iters + 1], info=info.as_dict())
+    if dump:
+        out.update(V=V, Z=Z, H=H, k=k.value)
+    return out

@@ -1,0 +1,281 @@
+"""Pins of the oracle's graph neural preconditioner (Sec. 2.3, Eqs. (4)-(6)).
+
+Each test checks a property fixed by the paper or by mathematics, chosen so
+that a dropped term, a transposed weight, a wrong Laplacian direction or a
+misplaced activation fails at least one of them:
+
+* closed-form outputs for hand-set weights (orientation of U, W, W1..W4,
+  placement of every ReLU);
+* the polynomial view: without active nonlinearity and with d = h = 1 the
+  network is c * prod_l (u_l I + w_l A-hat) applied to b (Sec. 1 remark on
+  GNNs becoming polynomials of A); the expected value is built from the
+  expanded polynomial coefficients and repeated scipy products;
+* scale equivariance (Eq. (6)) -- bit-exact for powers of two;
+* permutation equivariance and the L-hop receptive field;
+* the hand-written gradient against central finite differences and against
+  torch autograd on an independent re-expression of the forward pass.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from paper_2406_00809_amd import inputs as I
+
+
+def _pack(L, d, h, **kw):
+    lay = I.param_layout(L, d, h)
+    th = np.zeros(I.n_params(L, d, h))
+    for k, v in kw.items():
+        o, s = lay[k]
+        th[o:o + s] = np.asarray(v, dtype=np.float64).ravel()
+    return th
+
+
+def _sys(A):
+    return O.System(A, prescale=True)
+
+
+def test_param_count_matches_layout():
+    assert O.nparams(8, 16, 32) == I.n_params(8, 16, 32) == 5265
+    assert O.nparams(8, 32, 64) == I.n_params(8, 32, 64) == 20769
+    assert O.nparams(4, 16, 32) == 3217
+
+
+def test_pointwise_mlp_closed_form():
+    """L = 0, d = h = 2: hand-set weights give z = 2 max(b, 0).
+
+    W1 = [1, -1] -> hidden = (relu(u), relu(-u)); W2 = [[0,1],[7,0]] (input
+    index first) -> E = (7 relu(-u), relu(u)); W3 = [[0,0],[1,0]] reads
+    feature 1 into hidden 0; W4 = [2, 3] -> o = 2 relu(u); z = (tau/sqrt n) o.
+    A transposed W2 or W3 gives z = 0 or 14 max(-b,0)-type outputs instead.
+    """
+    S = _sys(I.laplace2d(6))
+    th = _pack(0, 2, 2, W1=[1, -1], W2=[[0, 1], [7, 0]], W3=[[0, 0], [1, 0]], W4=[2, 3])
+    b = np.random.default_rng(3).standard_normal(S.n)
+    z = O.gnp_forward(S, 0, 2, 2, th, b)
+    np.testing.assert_allclose(z, 2 * np.maximum(b, 0), rtol=1e-15, atol=1e-15)
+
+
+def test_bias_placement_closed_form():
+    """Biases: c1 shifts hidden, c2 shifts E, c3 shifts decoder hidden, c4 output.
+
+    L = 0, d = h = 1, W1 = 0 so hidden = relu(c1) = 2 (c1 = 2); W2 = 3 ->
+    E = 6 + c2 = 6 - 1 = 5; W3 = 1, c3 = -2 -> relu(3) = 3; W4 = 4, c4 = 0.5
+    -> o = 12.5; z = (tau/sqrt n) * 12.5 at every node.
+    """
+    S = _sys(I.laplace2d(5))
+    th = _pack(0, 1, 1, W1=[0], c1=[2], W2=[3], c2=[-1], W3=[1], c3=[-2], W4=[4], c4=[0.5])
+    b = np.random.default_rng(4).standard_normal(S.n)
+    z = O.gnp_forward(S, 0, 1, 1, th, b)
+    tau = np.linalg.norm(b)
+    np.testing.assert_allclose(z, np.full(S.n, tau / np.sqrt(S.n) * 12.5), rtol=1e-14)
+
+
+def _nonneg_system(n=40, seed=5):
+    A = I.random_small(n, 0.15, seed, nonneg=True)
+    return _sys(A)
+
+
+def test_layer_orientation_closed_form():
+    """One Res-GCONV layer, d = 2: U[0,1] routes feature 0 into feature 1.
+
+    Encoder writes u into feature 0 only, decoder reads feature 1 only.
+    With U[0,1] = 2, W = 0: z = 2 b for b > 0.  With U = 0, W[0,1] = 3:
+    z = 3 A-hat b (A-hat >= 0, b > 0 keep every ReLU active).
+    """
+    S = _nonneg_system()
+    b = np.random.default_rng(6).random(S.n) + 0.1
+    common = dict(W1=[1], W2=[[1, 0]], W3=[[0], [1]], W4=[1])
+    thU = _pack(1, 2, 1, U_0=[[0, 2], [0, 0]], **common)
+    zU = O.gnp_forward(S, 1, 2, 1, thU, b)
+    np.testing.assert_allclose(zU, 2 * b, rtol=1e-14)
+    thW = _pack(1, 2, 1, W_0=[[0, 3], [0, 0]], **common)
+    zW = O.gnp_forward(S, 1, 2, 1, thW, b)
+    Ahat = sp.csr_matrix((S.ahat, S.A.colind, S.A.rowptr), shape=(S.n, S.n))
+    np.testing.assert_allclose(zW, 3 * (Ahat @ b), rtol=1e-13)
+
+
+@pytest.mark.parametrize("L", [1, 3, 6])
+def test_polynomial_view(L):
+    """d = h = 1, zero biases, non-negative weights, A-hat >= 0, b > 0: every
+    ReLU is the identity and M(b) = c prod_l (u_l + w_l A-hat) b with
+    c = W1 W2 W3 W4.  Expected value from the expanded coefficients."""
+    S = _nonneg_system(n=60, seed=7)
+    rng = np.random.default_rng(L)
+    u = rng.random(L) + 0.1
+    w = rng.random(L) + 0.1
+    W1, W2, W3, W4 = rng.random(4) + 0.5
+    kw = dict(W1=[W1], W2=[W2], W3=[W3], W4=[W4])
+    for l in range(L):
+        kw[f"U_{l}"] = [u[l]]
+        kw[f"W_{l}"] = [w[l]]
+    th = _pack(L, 1, 1, **kw)
+    b = rng.random(S.n) + 0.1
+    z = O.gnp_forward(S, L, 1, 1, th, b)
+    coef = np.array([W1 * W2 * W3 * W4])
+    for l in range(L):
+        coef = np.polynomial.polynomial.polymul(coef, [u[l], w[l]])
+    Ahat = sp.csr_matrix((S.ahat, S.A.colind, S.A.rowptr), shape=(S.n, S.n))
+    expect = np.zeros(S.n)
+    p = b.copy()
+    for k, c in enumerate(coef):
+        expect += c * p
+        p = Ahat @ p
+    np.testing.assert_allclose(z, expect, rtol=1e-12)
+
+
+def _rand_model(S, L, d, h, seed):
+    return I.init_params(L, d, h, seed)
+
+
+@pytest.mark.parametrize("k", [-3, 1, 7])
+def test_scale_equivariance_power_of_two_bit_exact(k):
+    S = _sys(I.convdiff3d(6))
+    th = _rand_model(S, 3, 8, 16, 1)
+    b = np.random.default_rng(2).standard_normal(S.n)
+    z1 = O.gnp_forward(S, 3, 8, 16, th, b)
+    z2 = O.gnp_forward(S, 3, 8, 16, th, b * 2.0 ** k)
+    np.testing.assert_array_equal(z2, z1 * 2.0 ** k)
+
+
+def test_scale_equivariance_positive_alpha_and_zero():
+    S = _sys(I.convdiff3d(6))
+    th = _rand_model(S, 3, 8, 16, 3)
+    b = np.random.default_rng(4).standard_normal(S.n)
+    z1 = O.gnp_forward(S, 3, 8, 16, th, b)
+    z2 = O.gnp_forward(S, 3, 8, 16, th, 0.37 * b)
+    np.testing.assert_allclose(z2, 0.37 * z1, rtol=1e-13, atol=1e-15 * np.abs(z1).max())
+    # M(0) = 0 (tau = 0 maps to the zero vector)
+    np.testing.assert_array_equal(O.gnp_forward(S, 3, 8, 16, th, np.zeros(S.n)), np.zeros(S.n))
+    # negative alpha is NOT equivariant (ReLU is not odd) -- the reading for alpha > 0
+    z3 = O.gnp_forward(S, 3, 8, 16, th, -b)
+    assert np.linalg.norm(z3 + z1) > 1e-3 * np.linalg.norm(z1)
+
+
+def test_permutation_equivariance():
+    A = I.random_small(50, 0.1, 11)
+    perm = np.random.default_rng(12).permutation(50)
+    S, SP = _sys(A), _sys(I.permute(A, perm))
+    th = _rand_model(S, 4, 6, 12, 13)
+    b = np.random.default_rng(14).standard_normal(50)
+    bp = np.empty_like(b)
+    bp[perm] = b
+    z = O.gnp_forward(S, 4, 6, 12, th, b)
+    zp = O.gnp_forward(SP, 4, 6, 12, th, bp)
+    np.testing.assert_allclose(zp[perm], z, rtol=1e-12, atol=1e-12 * np.abs(z).max())
+
+
+def test_receptive_field_is_L_hops():
+    """z_i depends on b only through the L-hop out-neighbourhood of i in the
+    pattern of A (and through tau).  Changes outside move z_i only at rounding
+    level (via tau); a change one hop away moves it at O(1)."""
+    A = I.random_small(120, 0.012, 21, diag_shift=2.0)
+    S = _sys(A)
+    L = 2
+    th = _rand_model(S, L, 6, 12, 22)
+    rng = np.random.default_rng(23)
+    b = rng.standard_normal(S.n)
+    pat = (A.to_scipy() != 0).astype(np.int64)
+    reach = sp.identity(S.n, dtype=np.int64, format="csr")
+    for _ in range(L):
+        reach = ((reach + reach @ pat) != 0).astype(np.int64)
+    z = O.gnp_forward(S, L, 6, 12, th, b)
+    for i in rng.integers(0, S.n, 10):
+        inside = set(reach[i].indices)
+        outside = [j for j in range(S.n) if j not in inside]
+        j, k = outside[0], outside[-1]
+        bs = b.copy()
+        bs[j], bs[k] = b[k], b[j]  # keeps ||b|| up to summation rounding
+        zs = O.gnp_forward(S, L, 6, 12, th, bs)
+        assert abs(zs[i] - z[i]) <= 1e-13 * (abs(z[i]) + 1e-300) + 1e-15
+        nb = [q for q in pat[i].indices if q != i]
+        if nb:
+            bs = b.copy()
+            bs[nb[0]] += 1.0
+            bs *= np.linalg.norm(b) / np.linalg.norm(bs)
+            assert abs(O.gnp_forward(S, L, 6, 12, th, bs)[i] - z[i]) > 1e-9
+
+
+def _torch_forward(S, L, d, h, theta, b):
+    """Independent re-expression in torch FP64 (dense A-hat), used only to
+    cross-check the hand-written gradient with autograd."""
+    import torch
+    lay = I.param_layout(L, d, h)
+    P = lambda k, shp: theta[lay[k][0]:lay[k][0] + lay[k][1]].reshape(shp)
+    n = S.n
+    Ahat = torch.tensor(sp.csr_matrix((S.ahat, S.A.colind, S.A.rowptr), shape=(n, n)).toarray())
+    A = torch.tensor(S.A.to_scipy().toarray())
+    bt = torch.tensor(b)  # [n, B]
+    tau = torch.linalg.norm(bt, dim=0)
+    u = bt * (np.sqrt(n) / tau)
+    Hd = torch.relu(u[..., None] * P("W1", (h,)) + P("c1", (h,)))      # n,B,h
+    X = Hd @ P("W2", (h, d)) + P("c2", (d,))                            # n,B,d
+    for l in range(L):
+        T = torch.einsum("ij,jbf->ibf", Ahat, X)
+        X = torch.relu(X @ P(f"U_{l}", (d, d)) + T @ P(f"W_{l}", (d, d)))
+    o = torch.relu(X @ P("W3", (d, h)) + P("c3", (h,))) @ P("W4", (h,)) + P("c4", (1,))
+    z = o * (tau / np.sqrt(n))
+    R = A @ z - bt
+    return R.abs().mean(), z
+
+
+def test_gradient_matches_torch_autograd():
+    import torch
+    S = _sys(I.convdiff3d(5))
+    L, d, h, B = 3, 6, 10, 4
+    th0 = _rand_model(S, L, d, h, 31)
+    x = np.random.default_rng(32).standard_normal((S.n, B))
+    b = O.spmm(S.A, x)
+    loss, g = O.loss_grad(S, L, d, h, th0, b)
+    tht = torch.tensor(th0, requires_grad=True)
+    lt, zt = _torch_forward(S, L, d, h, tht, b)
+    lt.backward()
+    np.testing.assert_allclose(zt.detach().numpy(), O.gnp_forward(S, L, d, h, th0, b),
+                               rtol=1e-12, atol=1e-14)
+    assert abs(lt.item() - loss) <= 1e-13 * loss
+    np.testing.assert_allclose(g, tht.grad.numpy(), rtol=1e-10, atol=1e-13 * np.abs(g).max())
+
+
+def test_gradient_central_differences():
+    """Central differences (h = 1e-6, FP64) along random directions.  A
+    direction is used only when the step-h and step-h/2 quotients agree to
+    1e-7 (no ReLU or |.| kink crossed inside the stencil)."""
+    S = _sys(I.laplace2d(8))
+    L, d, h, B = 2, 4, 8, 3
+    th = _rand_model(S, L, d, h, 41)
+    rng = np.random.default_rng(42)
+    b = O.spmm(S.A, rng.standard_normal((S.n, B)))
+    _, g = O.loss_grad(S, L, d, h, th, b)
+    f = lambda t: O.loss_grad(S, L, d, h, t, b, want_grad=False)
+    used = 0
+    for _ in range(40):
+        v = rng.standard_normal(th.size)
+        v /= np.linalg.norm(v)
+        q1 = (f(th + 1e-6 * v) - f(th - 1e-6 * v)) / 2e-6
+        q2 = (f(th + 5e-7 * v) - f(th - 5e-7 * v)) / 1e-6
+        if abs(q1 - q2) > 1e-7 * max(abs(q1), 1e-3):
+            continue
+        used += 1
+        assert abs(q1 - g @ v) <= 1e-6 * max(abs(q1), 1e-3), (q1, g @ v)
+        if used >= 10:
+            break
+    assert used >= 10
+    # coordinate directions on a random subset of scalars
+    for k in rng.choice(th.size, 40, replace=False):
+        e = np.zeros(th.size)
+        e[k] = 1.0
+        q1 = (f(th + 1e-6 * e) - f(th - 1e-6 * e)) / 2e-6
+        q2 = (f(th + 5e-7 * e) - f(th - 5e-7 * e)) / 1e-6
+        if abs(q1 - q2) > 1e-7 * max(abs(q1), 1e-3):
+            continue
+        assert abs(q1 - g[k]) <= 1e-6 * max(abs(q1), 1e-3)
+
+
+def test_multi_rhs_columns_independent():
+    S = _sys(I.convdiff3d(5))
+    th = _rand_model(S, 2, 5, 7, 51)
+    bb = np.random.default_rng(52).standard_normal((S.n, 3))
+    Z = O.gnp_forward(S, 2, 5, 7, th, bb)
+    for c in range(3):
+        np.testing.assert_array_equal(Z[:, c], O.gnp_forward(S, 2, 5, 7, th, bb[:, c].copy()))
