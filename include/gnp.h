@@ -1,0 +1,179 @@
+/*
+ * gnp.h -- C ABI of libgnp: graph-neural-preconditioned flexible GMRES on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: J. Chen, "Graph Neural Preconditioners for Iterative Solutions of
+ * Sparse Linear Systems" (ICLR 2025).  Section numbers below refer to it.
+ *
+ * Conventions for every entry point
+ *  - Every call returns a gnp_status; no C++ exception crosses the ABI.  On a
+ *    status other than GNP_OK a thread-local message is available from
+ *    gnp_last_error().  Non-convergence of a solve is NOT an error: it returns
+ *    GNP_OK with info.converged = 0.
+ *  - Pointers named *_dev are device pointers (for example from PyTorch's
+ *    caching allocator); every other pointer is host memory.  The library
+ *    never frees memory it did not allocate.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *    ordered on that stream; calls that return host results synchronise it.
+ *  - Dense vectors with several right-hand sides are node-major: element
+ *    (i, k) of an n x nrhs block lives at [i * nrhs + k].
+ *  - CSR input: int32 rowptr[n+1] and colind[nnz], column indices sorted
+ *    and unique within each row, float64 values.
+ */
+#ifndef GNP_H
+#define GNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GNP_API __attribute__((visibility("default")))
+
+typedef enum {
+    GNP_OK = 0,
+    GNP_EINVAL = 1,   /* invalid argument or malformed CSR */
+    GNP_ENOMEM = 2,   /* device or host allocation failed */
+    GNP_EDEVICE = 3,  /* HIP runtime error */
+    GNP_ENUMERIC = 4, /* non-finite value met (b, weights, beta, h, tau, loss) */
+    GNP_EBUSY = 5     /* a served request is not finished yet */
+} gnp_status;
+
+/* Arithmetic of the preconditioned path.
+ *   GNP_F64 : everything in float64 (reference-precision instantiation).
+ *   GNP_F32 : network activations, SpMV and Krylov basis V, Z in float32.
+ *   GNP_BF16: network activations stored in bfloat16, products on MFMA with
+ *             float32 accumulation; SpMV and V, Z in float32.
+ * In every mode the Arnoldi inner products and norms, the Hessenberg
+ * least-squares (Givens), the solution x and the true residual b - A x are
+ * float64. */
+typedef enum { GNP_F64 = 0, GNP_F32 = 1, GNP_BF16 = 2 } gnp_precision;
+
+typedef struct gnp_system gnp_system;
+typedef struct gnp_model gnp_model;
+
+/* Message describing the last failure on the calling thread. */
+GNP_API const char *gnp_last_error(void);
+
+/* Library version string. */
+GNP_API const char *gnp_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Linear system                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Create a device-resident system from a host CSR matrix A (n x n).
+ *
+ * The host arrays are copied; the caller keeps them.  On the device the
+ * library computes gamma of Eq. (4) (an upper bound of the spectral radius
+ * by Gershgorin: min of the largest absolute row sum and the largest
+ * absolute column sum).  If prescale != 0, A is first divided by its own
+ * gamma (the harness normalisation of Sec. 3), and gamma is then recomputed
+ * for the scaled matrix.  A-hat = A / gamma (Eq. (4)) feeds the network; the
+ * (possibly prescaled) A is the matrix that fgmres_solve solves with.  The
+ * transposed CSR of A (needed by training) is built on the device by a
+ * counting sort.
+ *
+ * Errors: GNP_EINVAL when n < 1, nnz < 1, rowptr[0] != 0, rowptr is
+ * decreasing, rowptr[n] != nnz, a column index lies outside [0, n), columns
+ * in a row are not strictly increasing, a value is not finite, or gamma = 0.
+ */
+GNP_API gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr,
+                                     const int32_t *colind, const double *val, int prescale,
+                                     void *hip_stream, gnp_system **out);
+GNP_API void gnp_system_destroy(gnp_system *sys);
+
+/* gamma of the input matrix, and gamma of the matrix after the optional
+ * prescaling (the A-hat divisor).  Either pointer may be NULL. */
+GNP_API gnp_status gnp_system_gamma(const gnp_system *sys, double *gamma_input,
+                                    double *gamma_system);
+
+/* Copy device-resident arrays back to host buffers (any pointer may be NULL):
+ * val[nnz] = system A (float64), ahat[nnz] = A-hat (float64),
+ * t_rowptr[n+1], t_colind[nnz] = CSR of A^T, t_val[nnz] = values of A^T. */
+GNP_API gnp_status gnp_system_export(const gnp_system *sys, double *val, double *ahat,
+                                     int32_t *t_rowptr, int32_t *t_colind, double *t_val);
+
+GNP_API int64_t gnp_system_n(const gnp_system *sys);
+GNP_API int64_t gnp_system_nnz(const gnp_system *sys);
+
+/* y_dev = A x_dev (system matrix, Sec. 2.1).  prec = GNP_F64: float64 values,
+ * x and y float64; GNP_F32 / GNP_BF16: float32 values, x and y float32. */
+GNP_API gnp_status gnp_spmv(const gnp_system *sys, const void *x_dev, void *y_dev,
+                            gnp_precision prec, void *hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Graph neural preconditioner (Sec. 2.3)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Create the network M for a system: an MLP encoder lifting 1 -> d (hidden
+ * h), L Res-GCONV layers X <- ReLU(X U_l + A-hat X W_l) (Eq. (5)), an MLP
+ * decoder d -> 1 (hidden h), wrapped in the scale-equivariant s, s^-1 of
+ * Eq. (6) with tau = ||b||_2.
+ *
+ * Parameters are a float64 vector in this packing (matrices row-major with
+ * the input index first, y = x M):
+ *   W1[1 x h] c1[h] W2[h x d] c2[d] | for l < L: U_l[d x d] W_l[d x d] |
+ *   W3[d x h] c3[h] W4[h x 1] c4[1]
+ * count = 2h + 2hd + d + 2 L d^2 + 2h + 1.  init_params must hold that many
+ * values (the library has no random initialiser of its own).
+ * Supported (d, h): (16, 32) and (32, 64); 0 <= L <= 64.
+ * The model keeps a reference to sys, which must outlive it. */
+GNP_API gnp_status gnp_model_create(gnp_system *sys, int L, int d, int h,
+                                    const double *init_params, gnp_model **out);
+GNP_API void gnp_model_destroy(gnp_model *model);
+GNP_API size_t gnp_model_nparams(const gnp_model *model);
+GNP_API gnp_status gnp_params_get(const gnp_model *model, double *buf, size_t count);
+GNP_API gnp_status gnp_params_set(gnp_model *model, const double *buf, size_t count);
+
+/* z_dev = M(v_dev) for nrhs right-hand sides, node-major [n][nrhs].
+ * prec = GNP_F64: v, z float64; GNP_F32 / GNP_BF16: v, z float32.
+ * A zero column maps to a zero column (tau = 0).  Stream-ordered; uses the
+ * model's workspace (allocated on first use for a given nrhs, then reused).
+ * Errors: GNP_EINVAL for nrhs < 1 or a bad precision. */
+GNP_API gnp_status gnp_apply(gnp_model *model, const void *v_dev, void *z_dev, int nrhs,
+                             gnp_precision prec, void *hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* FGMRES(m) with the network as right preconditioner (Algorithm 1)         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int iters;          /* Arnoldi steps (applications of M), across restarts */
+    int restarts;       /* completed cycles that did not converge */
+    int converged;      /* 1 iff ||b - A x||_2 <= rtol ||b||_2 (true residual) */
+    int mismatch;       /* 1 iff true residual > 10 x the Givens estimate */
+    int breakdowns;     /* cycles ended by h_{j+1,j} <= 1e-14 ||A z_j|| */
+    double rel_res_true;/* ||b - A x|| / ||b|| at exit, float64 */
+    double rel_res_est; /* Givens least-squares estimate at exit */
+} gnp_solve_info;
+
+/* Solve A x = b (A = the system matrix) by restarted flexible GMRES.
+ *
+ * b_dev, x_dev: float64 device vectors of length n; x_dev holds x0 on entry
+ * and the solution on exit.  model = NULL runs unpreconditioned GMRES (M = I).
+ * m: restart length; rtol: relative tolerance on the true residual;
+ * maxiters: bound on Arnoldi steps across restarts.  After every Arnoldi step
+ * the Givens residual estimate is checked and ends the cycle early once it is
+ * below rtol ||b||; the float64 true residual confirms or restarts.
+ * Orthogonalisation is classical Gram-Schmidt applied twice with float64
+ * inner products.
+ * hist (optional, host, maxiters + 1 doubles): hist[0] = ||b - A x0||/||b||,
+ * hist[i] = estimated relative residual after Arnoldi step i; entries past
+ * info.iters are left untouched.
+ * b = 0 gives x = 0, iters = 0, converged = 1.
+ * Errors: GNP_EINVAL for m < 1, m > 256, rtol <= 0, maxiters < 1, a model of
+ * another system or a bad precision; GNP_ENUMERIC when b, the residual, a
+ * norm or a Hessenberg entry becomes non-finite. */
+GNP_API gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const double *b_dev,
+                                double *x_dev, int m, double rtol, int maxiters,
+                                gnp_precision prec, double *hist, gnp_solve_info *info,
+                                void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNP_H */

@@ -1,0 +1,169 @@
+"""Python-facing objects over the C ABI (include/gnp.h).
+
+Tensors are PyTorch device tensors; this module only checks shapes, dtypes
+and devices, and passes raw pointers and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GNP_BF16, GNP_F32, GNP_F64, GNPError, SolveInfo, check
+
+PREC = {"f64": GNP_F64, "f32": GNP_F32, "bf16": GNP_BF16,
+        GNP_F64: GNP_F64, GNP_F32: GNP_F32, GNP_BF16: GNP_BF16}
+KDTYPE = {GNP_F64: torch.float64, GNP_F32: torch.float32, GNP_BF16: torch.float32}
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype, numel=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+class System:
+    """Device-resident sparse system (gnp_system_create)."""
+
+    def __init__(self, csr=None, *, n=None, rowptr=None, colind=None, val=None,
+                 prescale: bool = True, stream=None):
+        if csr is not None:
+            n, rowptr, colind, val = csr.n, csr.rowptr, csr.colind, csr.val
+        L = _lib.load()
+        rp, prp = _host(rowptr, np.int32)
+        ci, pci = _host(colind, np.int32)
+        v, pv = _host(val, np.float64)
+        nnz = int(ci.size)
+        h = C.c_void_p()
+        check(L.gnp_system_create(int(n), nnz, prp, pci, pv, int(bool(prescale)),
+                                  _stream(stream), C.byref(h)))
+        self._h = h
+        self.n = int(n)
+        self.nnz = nnz
+        g0, g1 = C.c_double(), C.c_double()
+        check(L.gnp_system_gamma(h, C.byref(g0), C.byref(g1)))
+        self.gamma_input, self.gamma = g0.value, g1.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        L = _lib.load()
+        val = np.empty(self.nnz)
+        ahat = np.empty(self.nnz)
+        trp = np.empty(self.n + 1, dtype=np.int32)
+        tci = np.empty(self.nnz, dtype=np.int32)
+        tv = np.empty(self.nnz)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        check(L.gnp_system_export(self._h, p(val), p(ahat), p(trp), p(tci), p(tv)))
+        return dict(val=val, ahat=ahat, t_rowptr=trp, t_colind=tci, t_val=tv)
+
+    def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, prec="f32", stream=None):
+        p = PREC[prec]
+        dt = KDTYPE[p]
+        if y is None:
+            y = torch.empty(self.n, dtype=dt, device=x.device)
+        check(_lib.load().gnp_spmv(self._h, _dev_ptr(x, dt, self.n, "x"),
+                                   _dev_ptr(y, dt, self.n, "y"), p, _stream(stream)))
+        return y
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().gnp_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Model:
+    """Graph neural preconditioner bound to a System (gnp_model_create)."""
+
+    def __init__(self, system: System, L: int, d: int, h: int, params):
+        lib = _lib.load()
+        th, pth = _host(params, np.float64)
+        hm = C.c_void_p()
+        check(lib.gnp_model_create(system.handle, L, d, h, pth, C.byref(hm)))
+        self._h = hm
+        self.system = system  # keeps the system alive
+        self.L, self.d, self.h = L, d, h
+        self.nparams = int(lib.gnp_model_nparams(hm))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.nparams)
+        check(_lib.load().gnp_params_get(self._h, out.ctypes.data_as(C.c_void_p), self.nparams))
+        return out
+
+    def set_params(self, params):
+        th, pth = _host(params, np.float64)
+        check(_lib.load().gnp_params_set(self._h, pth, th.size))
+
+    def apply(self, v: torch.Tensor, z: torch.Tensor | None = None, prec="f32", stream=None):
+        """z = M(v); v of shape [n] or [n, nrhs] (node-major)."""
+        p = PREC[prec]
+        dt = KDTYPE[p]
+        nrhs = 1 if v.dim() == 1 else v.shape[1]
+        if z is None:
+            z = torch.empty_like(v)
+        check(_lib.load().gnp_apply(self._h, _dev_ptr(v, dt, self.system.n * nrhs, "v"),
+                                    _dev_ptr(z, dt, self.system.n * nrhs, "z"), nrhs, p,
+                                    _stream(stream)))
+        return z
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().gnp_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fgmres_solve(system: System, b: torch.Tensor, model: Model | None = None,
+                 x: torch.Tensor | None = None, m: int = 30, rtol: float = 1e-8,
+                 maxiters: int = 100, prec="f32", want_hist: bool = True, stream=None):
+    """Algorithm 1 on the device.  Returns (x, info dict, hist ndarray or None)."""
+    p = PREC[prec]
+    if x is None:
+        x = torch.zeros(system.n, dtype=torch.float64, device=b.device)
+    hist = np.full(maxiters + 1, np.nan) if want_hist else None
+    info = SolveInfo()
+    check(_lib.load().fgmres_solve(
+        system.handle, model.handle if model is not None else None,
+        _dev_ptr(b, torch.float64, system.n, "b"), _dev_ptr(x, torch.float64, system.n, "x"),
+        int(m), float(rtol), int(maxiters), p,
+        hist.ctypes.data_as(C.c_void_p) if hist is not None else None, C.byref(info),
+        _stream(stream)))
+    d = info.as_dict()
+    if hist is not None:
+        hist = hist[: d["iters"] + 1]
+    return x, d, hist

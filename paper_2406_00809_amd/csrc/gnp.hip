@@ -1,0 +1,330 @@
+// Graph neural preconditioner: model object, weight packing into MFMA
+// fragment layouts, column norms for the scaling s of Eq. (6), and the
+// forward launch sequence (encoder, L Res-GCONV layers, decoder).
+#include <math.h>
+
+#include <vector>
+
+#include "gnp_fwd.hpp"
+#include "model.hpp"
+
+namespace gnp {
+
+// ---------------------------------------------------------------------------
+// packing
+// ---------------------------------------------------------------------------
+__global__ void k_pack_bf16(const double *__restrict__ th, int64_t off, int K, int N,
+                            uint16_t *__restrict__ out, int64_t count) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const int i = (int)(p % 8), lane = (int)((p / 8) % 64);
+    const int64_t f = p / 512;
+    const int ntiles = N / 16;
+    const int nt = (int)(f % ntiles), kb = (int)(f / ntiles);
+    const int k = kb * 32 + 8 * (lane / 16) + i, col = nt * 16 + lane % 16;
+    const float v = k < K ? (float)th[off + (int64_t)k * N + col] : 0.f;
+    out[p] = f2bf(v);
+}
+
+__global__ void k_pack_f32(const double *__restrict__ th, int64_t off, int K, int N,
+                           float *__restrict__ out, int64_t count) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const int lane = (int)(p % 64);
+    const int64_t f = p / 64;
+    const int ntiles = N / 16;
+    const int nt = (int)(f % ntiles), ks = (int)(f / ntiles);
+    const int k = ks * 4 + lane / 16, col = nt * 16 + lane % 16;
+    out[p] = (float)th[off + (int64_t)k * N + col];
+}
+
+__global__ void k_copy_f32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) b[p] = (float)a[p];
+}
+
+gnp_status model_repack(gnp_model *m, hipStream_t st) {
+    const int L = m->L, d = m->d, h = m->h;
+    hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(m->np, BLOCK)), dim3(BLOCK), 0, st, m->theta64,
+                       m->theta32, m->np);
+    struct Mat { int64_t off; int K, N; int64_t pb, pf; };
+    std::vector<Mat> mats;
+    mats.push_back({m->po.W2, h, d, m->pb.W2, m->pf.W2});
+    for (int l = 0; l < L; ++l)
+        mats.push_back({m->po.U0 + (int64_t)l * 2 * d * d, 2 * d, d,
+                        m->pb.Wcat0 + l * m->pb.Wcat_stride, m->pf.Wcat0 + l * m->pf.Wcat_stride});
+    mats.push_back({m->po.W3, d, h, m->pb.W3, m->pf.W3});
+    for (const Mat &x : mats) {
+        const int64_t cb = pack_count_bf16(x.K, x.N), cf = pack_count_f32(x.K, x.N);
+        hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(cb, BLOCK)), dim3(BLOCK), 0, st, m->theta64,
+                           x.off, x.K, x.N, m->pk_bf16 + x.pb, cb);
+        hipLaunchKernelGGL(k_pack_f32, dim3(grid_for(cf, BLOCK)), dim3(BLOCK), 0, st, m->theta64,
+                           x.off, x.K, x.N, m->pk_f32 + x.pf, cf);
+    }
+    GNP_HIP(hipGetLastError());
+    return GNP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// column norms: tau_k = ||v(:, k)||_2 in float64, deterministic two stages
+// ---------------------------------------------------------------------------
+static int64_t colnorm_chunk(int64_t n) {
+    int64_t c = (n + 1023) / 1024;
+    return c < 512 ? 512 : c;
+}
+
+template <typename IN>
+__global__ __launch_bounds__(BLOCK) void k_colnorm(int64_t n, int B, int64_t chunk,
+                                                   const IN *__restrict__ v, double *partial,
+                                                   unsigned *counter, double *tau,
+                                                   const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ double sh[BLOCK];
+    const int t = threadIdx.x;
+    const int S = BLOCK / B;
+    const int c = t % B, p = t / B;
+    double s = 0.0;
+    if (p < S) {
+        const int64_t i0 = (int64_t)blockIdx.x * chunk;
+        const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+        for (int64_t i = i0 + p; i < i1; i += S) {
+            const double x = (double)v[i * B + c];
+            s += x * x;
+        }
+    }
+    sh[t] = s;
+    __syncthreads();
+    if (t < B) {
+        double a = 0.0;
+        for (int k = 0; k < S; ++k) a += sh[t + k * B];
+        partial[(int64_t)blockIdx.x * B + t] = a;
+    }
+    if (last_block(counter)) {
+        if (t < B) {
+            double a = 0.0;
+            for (unsigned blk = 0; blk < gridDim.x; ++blk) a += partial[(int64_t)blk * B + t];
+            const double tv = sqrt(a), sqn = sqrt((double)n);
+            tau[3 * t] = tv;
+            tau[3 * t + 1] = tv > 0.0 ? sqn / tv : 0.0;
+            tau[3 * t + 2] = tv / sqn;
+        }
+    }
+}
+
+template <typename IN>
+void launch_colnorm(gnp_model *m, const IN *v, int nrhs, double *tau_out, double *partial,
+                    unsigned *counter, const int *skip, hipStream_t st) {
+    const int64_t n = m->sys->n, chunk = colnorm_chunk(n);
+    const int nb = grid_for(n, (int)chunk);
+    hipLaunchKernelGGL(k_colnorm<IN>, dim3(nb), dim3(BLOCK), 0, st, n, nrhs, chunk, v, partial,
+                       counter, tau_out, skip);
+}
+template void launch_colnorm<float>(gnp_model *, const float *, int, double *, double *,
+                                    unsigned *, const int *, hipStream_t);
+template void launch_colnorm<double>(gnp_model *, const double *, int, double *, double *,
+                                     unsigned *, const int *, hipStream_t);
+
+gnp_status model_workspace(gnp_model *m, int nrhs) {
+    ApplyWorkspace &w = m->ws;
+    if (w.nrhs >= nrhs) return GNP_OK;
+    for (int i = 0; i < 2; ++i)
+        if (w.act[i]) (void)hipFree(w.act[i]);
+    if (w.tau) (void)hipFree(w.tau);
+    if (w.partial) (void)hipFree(w.partial);
+    if (w.counter) (void)hipFree(w.counter);
+    w = ApplyWorkspace();
+    const int64_t n = m->sys->n;
+    const size_t act_bytes = sizeof(double) * (size_t)n * nrhs * m->d;
+    for (int i = 0; i < 2; ++i) GNP_HIP(hipMalloc(&w.act[i], act_bytes));
+    GNP_HIP(hipMalloc(&w.tau, sizeof(double) * 3 * nrhs));
+    w.partial_blocks = grid_for(n, (int)colnorm_chunk(n));
+    GNP_HIP(hipMalloc(&w.partial, sizeof(double) * (size_t)w.partial_blocks * nrhs));
+    GNP_HIP(hipMalloc(&w.counter, sizeof(unsigned) * 4));
+    GNP_HIP(hipMemset(w.counter, 0, sizeof(unsigned) * 4));
+    w.nrhs = nrhs;
+    return GNP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// forward launch sequence
+// ---------------------------------------------------------------------------
+template <typename G, typename IN, typename ZT, int D, int H>
+static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const double *tau,
+                          G *act0, G *act1, const typename Act<G>::acc *vec, const void *wmat,
+                          const int *skip, hipStream_t st) {
+    gnp_system *s = m->sys;
+    const int64_t rows = s->n * (int64_t)nrhs;
+    const int grid = grid_for(rows, 64);
+    const ParamOffsets &po = m->po;
+    const typename Act<G>::vt *ahat;
+    const void *w2, *w3;
+    int64_t wstride, w0;
+    if constexpr (sizeof(G) == 8) {
+        ahat = (const typename Act<G>::vt *)s->ahat64;
+        w2 = m->theta64 + po.W2;
+        w3 = m->theta64 + po.W3;
+        w0 = po.U0;
+        wstride = 2 * (int64_t)D * D;
+    } else if constexpr (sizeof(G) == 4) {
+        ahat = (const typename Act<G>::vt *)s->ahat32;
+        w2 = m->pk_f32 + m->pf.W2;
+        w3 = m->pk_f32 + m->pf.W3;
+        w0 = m->pf.Wcat0;
+        wstride = m->pf.Wcat_stride;
+    } else {
+        ahat = (const typename Act<G>::vt *)s->ahat32;
+        w2 = m->pk_bf16 + m->pb.W2;
+        w3 = m->pk_bf16 + m->pb.W3;
+        w0 = m->pb.Wcat0;
+        wstride = m->pb.Wcat_stride;
+    }
+    auto wcat = [&](int l) -> const void * {
+        if constexpr (sizeof(G) == 8) return m->theta64 + w0 + l * wstride;
+        else if constexpr (sizeof(G) == 4) return m->pk_f32 + w0 + l * wstride;
+        else return m->pk_bf16 + w0 + l * wstride;
+    };
+    (void)wmat;
+    hipLaunchKernelGGL((k_encoder<G, IN, D, H>), dim3(grid), dim3(BLOCK), 0, st, rows, nrhs, v,
+                       tau, vec, po.W1, po.c1, po.c2, w2, act0, skip);
+    G *bufs[2] = {act0, act1};
+    for (int l = 0; l < m->L; ++l) {
+        const G *X = bufs[l % 2];
+        if (l < m->L - 1) {
+            hipLaunchKernelGGL((k_layer<G, D, H, false, ZT>), dim3(grid), dim3(BLOCK), 0, st, rows,
+                               nrhs, s->rp, s->ci, ahat, X, bufs[(l + 1) % 2], wcat(l), w3, vec,
+                               po.c3, po.W4, po.c4, tau, z, skip);
+        } else {
+            hipLaunchKernelGGL((k_layer<G, D, H, true, ZT>), dim3(grid), dim3(BLOCK), 0, st, rows,
+                               nrhs, s->rp, s->ci, ahat, X, (G *)nullptr, wcat(l), w3, vec, po.c3,
+                               po.W4, po.c4, tau, z, skip);
+        }
+    }
+}
+
+template <int D, int H>
+static void forward_dispatch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
+                             const double *tau, void *a0, void *a1, const int *skip,
+                             hipStream_t st) {
+    if (prec == GNP_F64)
+        forward_typed<double, double, double, D, H>(m, (const double *)v, (double *)z, nrhs, tau,
+                                                    (double *)a0, (double *)a1, m->theta64,
+                                                    nullptr, skip, st);
+    else if (prec == GNP_F32)
+        forward_typed<float, float, float, D, H>(m, (const float *)v, (float *)z, nrhs, tau,
+                                                 (float *)a0, (float *)a1, m->theta32, nullptr,
+                                                 skip, st);
+    else
+        forward_typed<uint16_t, float, float, D, H>(m, (const float *)v, (float *)z, nrhs, tau,
+                                                    (uint16_t *)a0, (uint16_t *)a1, m->theta32,
+                                                    nullptr, skip, st);
+}
+
+gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
+                          const double *tau, void *act0, void *act1, const int *skip,
+                          hipStream_t st) {
+    if (m->d == 16)
+        forward_dispatch<16, 32>(m, prec, v, z, nrhs, tau, act0, act1, skip, st);
+    else
+        forward_dispatch<32, 64>(m, prec, v, z, nrhs, tau, act0, act1, skip, st);
+    GNP_HIP(hipGetLastError());
+    return GNP_OK;
+}
+
+static void model_free(gnp_model *m) {
+    if (!m) return;
+    void *ptrs[] = {m->theta64, m->theta32, m->pk_bf16, m->pk_f32, m->ws.act[0], m->ws.act[1],
+                    m->ws.tau, m->ws.partial, m->ws.counter};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete m;
+}
+
+}  // namespace gnp
+
+using namespace gnp;
+
+extern "C" {
+
+gnp_status gnp_model_create(gnp_system *sys, int L, int d, int h, const double *init_params,
+                            gnp_model **out) {
+    if (!out) return fail(GNP_EINVAL, "out is null");
+    *out = nullptr;
+    if (!sys) return fail(GNP_EINVAL, "sys is null");
+    if (L < 1 || L > 64) return fail(GNP_EINVAL, "L must be in [1, 64]");
+    if (!((d == 16 && h == 32) || (d == 32 && h == 64)))
+        return fail(GNP_EINVAL, "supported (d, h): (16, 32), (32, 64)");
+    if (!init_params) return fail(GNP_EINVAL, "init_params is null");
+    gnp_model *m = new gnp_model();
+    m->sys = sys;
+    m->L = L;
+    m->d = d;
+    m->h = h;
+    m->po = param_offsets(L, d, h);
+    m->np = m->po.total;
+    for (int64_t k = 0; k < m->np; ++k)
+        if (!std::isfinite(init_params[k])) {
+            delete m;
+            return fail(GNP_ENUMERIC, "non-finite initial parameter at " + std::to_string(k));
+        }
+    m->pb = pack_offsets(L, d, h, true);
+    m->pf = pack_offsets(L, d, h, false);
+    auto run = [&]() -> gnp_status {
+        GNP_HIP(hipMalloc(&m->theta64, sizeof(double) * m->np));
+        GNP_HIP(hipMalloc(&m->theta32, sizeof(float) * m->np));
+        GNP_HIP(hipMalloc(&m->pk_bf16, sizeof(uint16_t) * m->pb.total));
+        GNP_HIP(hipMalloc(&m->pk_f32, sizeof(float) * m->pf.total));
+        GNP_HIP(hipMemcpy(m->theta64, init_params, sizeof(double) * m->np, hipMemcpyHostToDevice));
+        GNP_TRY(model_repack(m, nullptr));
+        GNP_HIP(hipStreamSynchronize(nullptr));
+        return GNP_OK;
+    };
+    gnp_status rc = run();
+    if (rc != GNP_OK) {
+        model_free(m);
+        return rc;
+    }
+    *out = m;
+    return GNP_OK;
+}
+
+void gnp_model_destroy(gnp_model *model) { model_free(model); }
+
+size_t gnp_model_nparams(const gnp_model *model) { return model ? (size_t)model->np : 0; }
+
+gnp_status gnp_params_get(const gnp_model *m, double *buf, size_t count) {
+    if (!m || !buf) return fail(GNP_EINVAL, "null argument");
+    if (count != (size_t)m->np) return fail(GNP_EINVAL, "count must equal the parameter count");
+    GNP_HIP(hipMemcpy(buf, m->theta64, sizeof(double) * m->np, hipMemcpyDeviceToHost));
+    return GNP_OK;
+}
+
+gnp_status gnp_params_set(gnp_model *m, const double *buf, size_t count) {
+    if (!m || !buf) return fail(GNP_EINVAL, "null argument");
+    if (count != (size_t)m->np) return fail(GNP_EINVAL, "count must equal the parameter count");
+    for (size_t k = 0; k < count; ++k)
+        if (!std::isfinite(buf[k])) return fail(GNP_ENUMERIC, "non-finite parameter");
+    GNP_HIP(hipDeviceSynchronize());
+    GNP_HIP(hipMemcpy(m->theta64, buf, sizeof(double) * m->np, hipMemcpyHostToDevice));
+    GNP_TRY(model_repack(m, nullptr));
+    GNP_HIP(hipStreamSynchronize(nullptr));
+    return GNP_OK;
+}
+
+gnp_status gnp_apply(gnp_model *m, const void *v_dev, void *z_dev, int nrhs, gnp_precision prec,
+                     void *hip_stream) {
+    if (!m || !v_dev || !z_dev) return fail(GNP_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > BLOCK) return fail(GNP_EINVAL, "nrhs must be in [1, 256]");
+    if (!valid_precision(prec)) return fail(GNP_EINVAL, "bad precision");
+    hipStream_t st = (hipStream_t)hip_stream;
+    GNP_TRY(model_workspace(m, nrhs));
+    ApplyWorkspace &w = m->ws;
+    if (prec == GNP_F64)
+        launch_colnorm<double>(m, (const double *)v_dev, nrhs, w.tau, w.partial, w.counter,
+                               nullptr, st);
+    else
+        launch_colnorm<float>(m, (const float *)v_dev, nrhs, w.tau, w.partial, w.counter, nullptr,
+                              st);
+    return forward_launch(m, prec, v_dev, z_dev, nrhs, w.tau, w.act[0], w.act[1], nullptr, st);
+}
+
+}  // extern "C"

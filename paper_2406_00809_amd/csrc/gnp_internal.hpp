@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP translation units of libgnp.
+// Device helpers: wavefront/block reductions, the deterministic "last block"
+// grid reduction, bf16 conversion and MFMA operand vector types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+
+#include "../../include/gnp.h"
+
+namespace gnp {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+
+// ---------------------------------------------------------------------------
+// error plumbing (host)
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+gnp_status fail(gnp_status st, const std::string &msg);
+gnp_status check_hip(hipError_t e, const char *what);
+
+#define GNP_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t e__ = (call);                                        \
+        if (e__ != hipSuccess) return ::gnp::check_hip(e__, #call);     \
+    } while (0)
+
+#define GNP_TRY(call)                                                   \
+    do {                                                                \
+        gnp_status s__ = (call);                                        \
+        if (s__ != GNP_OK) return s__;                                  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// conversions
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ float to_f32(T v) { return (float)v; }
+template <> __device__ __forceinline__ float to_f32<__bf16>(__bf16 v) { return (float)v; }
+
+template <typename T> __device__ __forceinline__ T from_acc(float v) { return (T)v; }
+template <typename T> __device__ __forceinline__ T from_acc(double v) { return (T)v; }
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// Sum over the block in a fixed order (deterministic).  All threads must
+// call it; the result is valid in every thread.  `scratch` holds BLOCK/WAVE
+// doubles.
+__device__ __forceinline__ double block_sum(double v, double *scratch) {
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) scratch[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) s += scratch[i];
+    return s;
+}
+
+// Grid-level "last block" detection for deterministic two-stage reductions:
+// every block writes its partials, then calls this; exactly one block (the
+// last to arrive) gets true and may read all partials, which it sums in
+// block order.  The ticket counter is reset by that block.
+__device__ __forceinline__ bool last_block(unsigned *counter) {
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(counter, 1u);
+        is_last = (t == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (is_last) {
+        __threadfence();
+        if (threadIdx.x == 0) atomicExch(counter, 0u);
+    }
+    return is_last != 0;
+}
+
+// ---------------------------------------------------------------------------
+// precision selection
+// ---------------------------------------------------------------------------
+inline bool valid_precision(int p) { return p == GNP_F64 || p == GNP_F32 || p == GNP_BF16; }
+
+inline int grid_for(int64_t work, int per_block, int cap = 1 << 20) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace gnp
+
+// ---------------------------------------------------------------------------
+// objects behind the opaque handles
+// ---------------------------------------------------------------------------
+struct gnp_system {
+    int64_t n = 0, nnz = 0;
+    int max_row = 0;
+    int32_t *rp = nullptr, *ci = nullptr;        // CSR of A (device)
+    double *val64 = nullptr;                     // system A, float64
+    float *val32 = nullptr;                      // system A, float32
+    double *ahat64 = nullptr;                    // A-hat = A / gamma
+    float *ahat32 = nullptr;
+    int32_t *trp = nullptr, *tci = nullptr;      // CSR of A^T
+    double *tval64 = nullptr;                    // A^T
+    float *tval32 = nullptr;
+    double *tahat64 = nullptr;                   // A-hat^T
+    float *tahat32 = nullptr;
+    double gamma_raw = 0.0, gamma = 0.0;
+    unsigned *counters = nullptr;                // tickets for last-block reductions
+    double *scratch = nullptr;                   // small reduction scratch
+    int nscratch = 0;
+    void *solve_cache = nullptr;                 // FGMRES workspace of fgmres_solve
+};
+
+namespace gnp {
+void solve_cache_free(void *p);
+}

@@ -1,0 +1,103 @@
+// Network object and the internal launch interface of the forward pass.
+#pragma once
+#include "gnp_internal.hpp"
+
+namespace gnp {
+
+// bf16 held as raw 16-bit words in memory; conversions are explicit.
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+struct ParamOffsets {
+    int64_t W1, c1, W2, c2, W3, c3, W4, c4;
+    int64_t U0;  // U_l at U0 + l * 2 d^2, W_l right after it
+    int64_t total;
+};
+
+inline ParamOffsets param_offsets(int L, int d, int h) {
+    ParamOffsets o;
+    o.W1 = 0;
+    o.c1 = h;
+    o.W2 = 2 * h;
+    o.c2 = o.W2 + (int64_t)h * d;
+    o.U0 = o.c2 + d;
+    o.W3 = o.U0 + (int64_t)L * 2 * d * d;
+    o.c3 = o.W3 + (int64_t)d * h;
+    o.W4 = o.c3 + h;
+    o.c4 = o.W4 + h;
+    o.total = o.c4 + 1;
+    return o;
+}
+
+// Offsets (in elements) of the MFMA-fragment packings of the three matrix
+// kinds.  bf16 fragments: 16x16x32 B-operand, K padded to a multiple of 32;
+// f32 fragments: 16x16x4 B-operand.
+struct PackOffsets {
+    int64_t W2, Wcat0, Wcat_stride, W3, total;
+};
+
+inline int64_t pack_count_bf16(int K, int N) { return (int64_t)((K + 31) / 32) * (N / 16) * 512; }
+inline int64_t pack_count_f32(int K, int N) { return (int64_t)(K / 4) * (N / 16) * 64; }
+
+inline PackOffsets pack_offsets(int L, int d, int h, bool bf16) {
+    PackOffsets p;
+    auto cnt = [&](int K, int N) { return bf16 ? pack_count_bf16(K, N) : pack_count_f32(K, N); };
+    p.W2 = 0;
+    p.Wcat0 = cnt(h, d);
+    p.Wcat_stride = cnt(2 * d, d);
+    p.W3 = p.Wcat0 + (int64_t)L * p.Wcat_stride;
+    p.total = p.W3 + cnt(d, h);
+    return p;
+}
+
+struct ApplyWorkspace {
+    int nrhs = 0;
+    void *act[2] = {nullptr, nullptr};  // ping-pong activations, n*nrhs*d (sized for f64)
+    double *tau = nullptr;              // [3 * nrhs]: tau, sqrt(n)/tau, tau/sqrt(n)
+    double *partial = nullptr;          // column-norm partials
+    unsigned *counter = nullptr;
+    int partial_blocks = 0;
+};
+
+}  // namespace gnp
+
+struct gnp_model {
+    gnp_system *sys = nullptr;
+    int L = 0, d = 0, h = 0;
+    int64_t np = 0;
+    double *theta64 = nullptr;     // master parameters (device, float64)
+    float *theta32 = nullptr;      // float32 copy (biases and vectors)
+    uint16_t *pk_bf16 = nullptr;   // bf16 MFMA fragments
+    float *pk_f32 = nullptr;       // f32 MFMA fragments
+    gnp::ParamOffsets po;
+    gnp::PackOffsets pb, pf;
+    gnp::ApplyWorkspace ws;
+};
+
+namespace gnp {
+
+// Repack the fragment layouts and float32 copy from theta64 (stream-ordered).
+gnp_status model_repack(gnp_model *m, hipStream_t st);
+
+// Make sure the apply workspace can hold nrhs right-hand sides.
+gnp_status model_workspace(gnp_model *m, int nrhs);
+
+// Column norms of v ([n][nrhs], float or double) into tau triples
+// (tau, sqrt(n)/tau, tau/sqrt(n)) at tau_out[3*k .. 3*k+2].
+template <typename IN>
+void launch_colnorm(gnp_model *m, const IN *v, int nrhs, double *tau_out, double *partial,
+                    unsigned *counter, const int *skip, hipStream_t st);
+
+// z = M(v) given precomputed tau triples.  act0/act1: activation buffers.
+// When acts_out != nullptr, layer inputs X_0..X_{L-1} are written to
+// acts_out + l * n * nrhs * d (training forward) instead of ping-ponging.
+gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
+                          const double *tau, void *act0, void *act1, const int *skip,
+                          hipStream_t st);
+
+}  // namespace gnp

@@ -1,0 +1,62 @@
+// FGMRES(m) solve context: device workspace and the device-resident control
+// block that lets every kernel of an Arnoldi step exit early once the cycle
+// has ended (Givens estimate below target, breakdown, or iteration limit),
+// so the host synchronises only once per restart cycle.
+#pragma once
+#include "gnp_internal.hpp"
+#include "model.hpp"
+
+namespace gnp {
+
+struct Ctl {
+    int cycle_done;  // step kernels exit at entry when set
+    int kcols;       // Arnoldi steps completed in the current cycle
+    int kuse;        // columns used by the least-squares solution
+    int it;          // Arnoldi steps in total
+    int converged;
+    int breakdowns;
+    int restarts;
+    int nonfinite;
+    int solve_done;
+    int m, maxiters, pad_;
+    double bnorm, target, beta, est, rel_true, wnorm0, hnext, est_rel;
+};
+
+struct SolveCtx {
+    gnp_system *sys = nullptr;
+    int m = 0;
+    int maxiters_cap = 0;
+    gnp_precision prec = GNP_F32;
+    int64_t n = 0;
+    size_t kbytes = 4;      // bytes per Krylov element
+    void *V = nullptr;      // (m+1) x n
+    void *Z = nullptr;      // m x n
+    void *w = nullptr;      // n
+    double *r = nullptr;    // n, float64 residual
+    void *act[2] = {nullptr, nullptr};
+    int act_d = 0;
+    double *tau = nullptr;  // tau triple for the network input
+    double *H = nullptr;    // (m+1) x m, rotated (upper triangle + zeros)
+    double *H0 = nullptr;   // (m+1) x m, as built
+    double *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+    double *h1 = nullptr, *h2 = nullptr;  // CGS2 pass coefficients
+    double *hist = nullptr;               // maxiters_cap + 1
+    double *partial = nullptr;
+    int64_t npartial = 0;
+    unsigned *counters = nullptr;
+    Ctl *ctl = nullptr;
+    Ctl *ctl_host = nullptr;  // pinned
+    hipEvent_t ev = nullptr;
+};
+
+gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
+                             gnp_precision prec, int act_d);
+void solve_ctx_free(SolveCtx *c);
+
+// Enqueue the whole solve on `st` and run it to completion (one host sync per
+// cycle).  x holds x0 on entry.
+gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, int m,
+                     double rtol, int maxiters, double *hist_host, gnp_solve_info *info,
+                     hipStream_t st);
+
+}  // namespace gnp

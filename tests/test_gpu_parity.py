@@ -1,0 +1,250 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: integer / CSR work bit-exact; float64 instantiation ~1e-12; float32
+network 1e-5 and bfloat16 network 3e-2, both normwise relative per
+right-hand side ||z - z_ref|| / ||z_ref||; every solve reaches the same rtol
+with iteration counts within max(1, ceil(10%)) of the oracle.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_00809_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 3e-2}
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    from paper_2406_00809_amd import api as A
+    return A
+
+
+def _dev(x, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _kdt(prec):
+    import torch
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+def _relerr(z, ref):
+    z = np.asarray(z, dtype=np.float64).reshape(ref.shape)
+    if ref.ndim == 1:
+        return np.linalg.norm(z - ref) / max(np.linalg.norm(ref), 1e-300)
+    return max(np.linalg.norm(z[:, k] - ref[:, k]) / max(np.linalg.norm(ref[:, k]), 1e-300)
+               for k in range(ref.shape[1]))
+
+
+def test_single_hip_runtime_loaded(api):
+    import torch
+    S = api.System(I.laplace2d(4))
+    torch.cuda.synchronize()
+    maps = open("/proc/self/maps").read()
+    libs = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(libs) == 1, libs
+    assert any("libgnp.so" in l for l in maps.splitlines())
+    del S
+
+
+@pytest.mark.parametrize("name", ["laplace2d_32", "convdiff3d_16", "powerlaw_20000",
+                                  "random_37"])
+@pytest.mark.parametrize("prescale", [True, False])
+def test_system_gamma_transpose_bit_exact(api, name, prescale):
+    A = {"laplace2d_32": lambda: I.laplace2d(32), "convdiff3d_16": lambda: I.convdiff3d(16),
+         "powerlaw_20000": lambda: I.powerlaw_random(20000, seed_structure=5, seed_values=6),
+         "random_37": lambda: I.random_small(37, 0.2, 3)}[name]()
+    S = api.System(A, prescale=prescale)
+    ref = O.System(A, prescale=prescale)
+    assert S.gamma_input == ref.gamma_raw
+    assert S.gamma == ref.gamma
+    ex = S.export()
+    np.testing.assert_array_equal(ex["val"], ref.A.val)
+    np.testing.assert_array_equal(ex["ahat"], ref.ahat)
+    T = O.transpose(ref.A)
+    np.testing.assert_array_equal(ex["t_rowptr"], T.rowptr)
+    np.testing.assert_array_equal(ex["t_colind"], T.colind)
+    np.testing.assert_array_equal(ex["t_val"], T.val)
+
+
+@pytest.mark.parametrize("name", ["convdiff3d_20", "powerlaw_30000", "tiny_3"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_spmv(api, name, prec):
+    A = {"convdiff3d_20": lambda: I.convdiff3d(20),
+         "powerlaw_30000": lambda: I.powerlaw_random(30000, seed_structure=7, seed_values=8),
+         "tiny_3": lambda: I.laplace2d(3)}[name]()
+    S = api.System(A)
+    ref = O.System(A)
+    x = np.random.default_rng(1).standard_normal(A.n)
+    y = S.spmv(_dev(x, _kdt(prec)), prec=prec).cpu().numpy()
+    yr = O.spmm(ref.A, x)
+    tol = 1e-14 if prec == "f64" else 2e-6
+    assert _relerr(y, yr) < tol
+
+
+CASES = {
+    # name: (matrix, L, d, h)
+    "c1_laplace2d_32": (lambda: I.laplace2d(32), 4, 16, 32),
+    "ragged_laplace2d_30": (lambda: I.laplace2d(30), 3, 16, 32),
+    "tiny_laplace2d_3": (lambda: I.laplace2d(3), 2, 16, 32),
+    "convdiff3d_16_d32": (lambda: I.convdiff3d(16), 8, 32, 64),
+    "powerlaw_20000_d32": (lambda: I.powerlaw_random(20000, seed_structure=9, seed_values=10),
+                           8, 32, 64),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_gnp_apply_single_rhs(api, case, prec):
+    mk, L, d, h = CASES[case]
+    A = mk()
+    S = api.System(A)
+    ref = O.System(A)
+    th = I.init_params(L, d, h, 11)
+    M = api.Model(S, L, d, h, th)
+    np.testing.assert_array_equal(M.get_params(), th)
+    v = np.random.default_rng(2).standard_normal(A.n)
+    z = M.apply(_dev(v, _kdt(prec)), prec=prec).cpu().numpy()
+    zr = O.gnp_forward(ref, L, d, h, th, v)
+    err = _relerr(z, zr)
+    print(f"{case} {prec}: rel err {err:.3e}")
+    assert err < TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [3, 32])
+def test_gnp_apply_multi_rhs_and_zero_column(api, prec, nrhs):
+    A = I.convdiff3d(10)
+    S = api.System(A)
+    ref = O.System(A)
+    L, d, h = 4, 32, 64
+    th = I.init_params(L, d, h, 12)
+    M = api.Model(S, L, d, h, th)
+    v = np.random.default_rng(3).standard_normal((A.n, nrhs))
+    v[:, 1] = 0.0
+    v[:, 2] *= 1e-3
+    z = M.apply(_dev(v, _kdt(prec)), prec=prec).cpu().numpy().reshape(A.n, nrhs)
+    zr = O.gnp_forward(ref, L, d, h, th, v)
+    assert np.all(z[:, 1] == 0.0)
+    cols = [k for k in range(nrhs) if k != 1]
+    assert _relerr(z[:, cols], zr[:, cols]) < TOL[prec]
+
+
+def test_gnp_apply_scale_equivariance_bit_exact(api):
+    A = I.convdiff3d(12)
+    S = api.System(A)
+    L, d, h = 3, 32, 64
+    M = api.Model(S, L, d, h, I.init_params(L, d, h, 13))
+    v = np.random.default_rng(4).standard_normal(A.n)
+    for prec in ("f64", "f32", "bf16"):
+        z1 = M.apply(_dev(v, _kdt(prec)), prec=prec).cpu().numpy()
+        z2 = M.apply(_dev(v * 8.0, _kdt(prec)), prec=prec).cpu().numpy()
+        np.testing.assert_array_equal(z2, 8.0 * z1)
+
+
+def test_params_set_roundtrip(api):
+    A = I.laplace2d(8)
+    S = api.System(A)
+    M = api.Model(S, 2, 16, 32, I.init_params(2, 16, 32, 1))
+    th = I.init_params(2, 16, 32, 2)
+    M.set_params(th)
+    np.testing.assert_array_equal(M.get_params(), th)
+    v = np.random.default_rng(5).standard_normal(A.n)
+    z = M.apply(_dev(v, _kdt("f64")), prec="f64").cpu().numpy()
+    zr = O.gnp_forward(O.System(A), 2, 16, 32, th, v)
+    assert _relerr(z, zr) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# FGMRES
+# ---------------------------------------------------------------------------
+
+def _iters_close(it, it_ref):
+    return abs(it - it_ref) <= max(1, int(np.ceil(0.1 * it_ref)))
+
+
+@pytest.mark.parametrize("m", [10, 30])
+def test_fgmres_identity_f64_matches_oracle(api, m):
+    A = I.convdiff3d(12)
+    S = api.System(A)
+    ref = O.System(A)
+    b = np.random.default_rng(6).standard_normal(A.n)
+    x, info, hist = api.fgmres_solve(S, _dev(b, _kdt("f64")), None, m=m, rtol=1e-8,
+                                     maxiters=2000, prec="f64")
+    r = O.fgmres(ref, b, m, 1e-8, 2000, ortho=O.CGS2)
+    assert info["converged"] == 1 and r["info"]["converged"] == 1
+    assert info["iters"] == r["info"]["iters"]
+    assert info["restarts"] == r["info"]["restarts"]
+    np.testing.assert_allclose(hist, r["hist"], rtol=1e-9)
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(xs - r["x"]) <= 1e-9 * np.linalg.norm(r["x"])
+    true = np.linalg.norm(b - ref.A.to_scipy() @ xs) / np.linalg.norm(b)
+    assert true <= 1e-8 and abs(true - info["rel_res_true"]) <= 1e-6 * true
+
+
+def test_fgmres_c1_trained_f64_matches_oracle(api):
+    """C1: 2D Laplacian 32x32, oracle-trained GNP (L=4,d=16,h=32), FGMRES(10)."""
+    A = I.laplace2d(32)
+    th = np.load(os.path.join(GOLD, "c1_gnp_oracle_trained.npy"))
+    S = api.System(A)
+    ref = O.System(A)
+    M = api.Model(S, 4, 16, 32, th)
+    b = I.rhs_normal(A.n, 0)
+    x, info, hist = api.fgmres_solve(S, _dev(b, _kdt("f64")), M, m=10, rtol=1e-8,
+                                     maxiters=3000, prec="f64")
+    r = O.fgmres(ref, b, 10, 1e-8, 3000, M="gnp", theta=th, arch=(4, 16, 32), ortho=O.CGS2)
+    print("gpu", info, "oracle", r["info"])
+    assert info["converged"] == 1 and r["info"]["converged"] == 1
+    assert _iters_close(info["iters"], r["info"]["iters"])
+    n0 = min(len(hist), len(r["hist"]), 11)
+    np.testing.assert_allclose(hist[:n0], r["hist"][:n0], rtol=1e-8)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_fgmres_c1_trained_reduced_precision(api, prec):
+    A = I.laplace2d(32)
+    th = np.load(os.path.join(GOLD, "c1_gnp_oracle_trained.npy"))
+    S = api.System(A)
+    ref = O.System(A)
+    M = api.Model(S, 4, 16, 32, th)
+    b = I.rhs_normal(A.n, 0)
+    x, info, hist = api.fgmres_solve(S, _dev(b, _kdt("f64")), M, m=10, rtol=1e-8,
+                                     maxiters=3000, prec=prec)
+    r = O.fgmres(ref, b, 10, 1e-8, 3000, M="gnp", theta=th, arch=(4, 16, 32), ortho=O.CGS2)
+    print(prec, "gpu", info, "oracle", r["info"])
+    xs = x.cpu().numpy()
+    true = np.linalg.norm(b - ref.A.to_scipy() @ xs) / np.linalg.norm(b)
+    assert info["converged"] == 1 and true <= 1e-8
+    assert _iters_close(info["iters"], r["info"]["iters"]), (info["iters"], r["info"]["iters"])
+
+
+def test_fgmres_edge_cases(api):
+    import torch
+    A = I.laplace2d(6)
+    S = api.System(A)
+    z = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    x, info, hist = api.fgmres_solve(S, z, None, m=5, rtol=1e-8, maxiters=50, prec="f32")
+    assert info["iters"] == 0 and info["converged"] == 1 and torch.all(x == 0)
+    b = _dev(np.random.default_rng(7).standard_normal(A.n), torch.float64)
+    x, info, hist = api.fgmres_solve(S, b, None, m=5, rtol=1e-8, maxiters=1, prec="f32")
+    assert info["iters"] == 1 and info["converged"] == 0
+    from paper_2406_00809_amd._lib import GNPError
+    for kw in (dict(m=0), dict(rtol=0.0), dict(maxiters=0), dict(m=300)):
+        args = dict(m=5, rtol=1e-8, maxiters=10)
+        args.update(kw)
+        with pytest.raises(GNPError):
+            api.fgmres_solve(S, b, None, prec="f32", **args)
+    bad = b.clone()
+    bad[3] = float("nan")
+    with pytest.raises(GNPError):
+        api.fgmres_solve(S, bad, None, m=5, rtol=1e-8, maxiters=10, prec="f32")
