@@ -127,6 +127,10 @@ GNP_API void gnp_model_destroy(gnp_model *model);
 GNP_API size_t gnp_model_nparams(const gnp_model *model);
 GNP_API gnp_status gnp_params_get(const gnp_model *model, double *buf, size_t count);
 GNP_API gnp_status gnp_params_set(gnp_model *model, const double *buf, size_t count);
+/* Same as gnp_params_set from a float64 device buffer, stream-ordered (no
+ * host synchronisation, no finiteness check). */
+GNP_API gnp_status gnp_params_set_device(gnp_model *model, const double *buf_dev, size_t count,
+                                         void *hip_stream);
 
 /* z_dev = M(v_dev) for nrhs right-hand sides, node-major [n][nrhs].
  * prec = GNP_F64: v, z float64; GNP_F32 / GNP_BF16: v, z float32.
@@ -170,6 +174,59 @@ typedef struct {
 GNP_API gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const double *b_dev,
                                 double *x_dev, int m, double rtol, int maxiters,
                                 gnp_precision prec, double *hist, gnp_solve_info *info,
+                                void *hip_stream);
+
+
+/* ------------------------------------------------------------------------ */
+/* Training (Sec. 2.2 and Sec. 3 "Hyperparameters")                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int steps;           /* Adam steps */
+    int batch;           /* right-hand sides per step, 1..256 */
+    double lr;           /* Adam learning rate (the paper uses 1e-3) */
+    double beta1, beta2; /* Adam moment decay rates (0.9, 0.999) */
+    double eps;          /* Adam epsilon (1e-8) */
+    uint64_t seed;       /* seed of the x ~ N(0, I) sampler */
+    gnp_precision prec;  /* GNP_F32 or GNP_F64 */
+} gnp_train_opts;
+
+/* Train the network on streaming pairs (b = A x, x): every step draws
+ * x ~ N(0, I) ([n][batch]) with a counter-based Philox4x32-10 generator
+ * (counter = (element index low, high, step, 0), key = seed) and the
+ * Box-Muller transform, unless x_fixed_dev (float64 device, [n][batch]) is
+ * given, in which case that batch is used at every step.  Loss: mean over the
+ * n*batch entries of |A M(b) - b| (the l1 residual of Sec. 3); gradient by the
+ * hand-written backward; update: bias-corrected Adam on float64 master
+ * weights.  At the end the model holds the weights of the step with the
+ * smallest loss (earliest on ties), as the paper keeps the best epoch.
+ * loss_hist (host, optional, [steps]) receives the loss of every step;
+ * *best_step its index.  Synchronises the stream.
+ * Errors: GNP_EINVAL for bad options or precision GNP_BF16; GNP_ENUMERIC if a
+ * loss is not finite (updates stop at that step). */
+GNP_API gnp_status gnp_train(gnp_model *model, const gnp_train_opts *opts,
+                             const double *x_fixed_dev, double *loss_hist, int *best_step,
+                             void *hip_stream);
+
+/* Loss and gradient at the current weights for one batch b_dev (float64
+ * device, [n][nrhs]): *loss = mean |A M(b) - b|, grad (host, optional,
+ * [nparams]) = its gradient in the packing of gnp_model_create.  prec:
+ * GNP_F32 or GNP_F64.  Synchronises the stream. */
+GNP_API gnp_status gnp_loss_grad(gnp_model *model, const double *b_dev, int nrhs,
+                                 gnp_precision prec, double *loss, double *grad,
+                                 void *hip_stream);
+
+/* Forward pass that keeps every layer input for a later gnp_backward (the
+ * pair behind a torch.autograd.Function).  b_dev, z_dev: [n][nrhs] in the
+ * precision's type (float64 or float32).  The saved state belongs to the
+ * model and is replaced by the next call. */
+GNP_API gnp_status gnp_forward_save(gnp_model *model, const void *b_dev, void *z_dev, int nrhs,
+                                    gnp_precision prec, void *hip_stream);
+
+/* Vector-Jacobian product of the last gnp_forward_save: given dz_dev
+ * ([n][nrhs], same type), write d<dz, M(b)>/dtheta to dparams_dev (float64
+ * device, [nparams]).  Errors: GNP_EINVAL without a saved forward. */
+GNP_API gnp_status gnp_backward(gnp_model *model, const void *dz_dev, double *dparams_dev,
                                 void *hip_stream);
 
 #ifdef __cplusplus

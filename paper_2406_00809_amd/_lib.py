@@ -24,6 +24,12 @@ GNP_F64, GNP_F32, GNP_BF16 = 0, 1, 2
 VP, I32P, F64P = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)
 
 
+class TrainOpts(C.Structure):
+    _fields_ = [("steps", C.c_int), ("batch", C.c_int), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("seed", C.c_uint64), ("prec", C.c_int)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
                 ("mismatch", C.c_int), ("breakdowns", C.c_int),
@@ -49,9 +55,14 @@ SIGNATURES = {
     "gnp_model_nparams": (C.c_size_t, [VP]),
     "gnp_params_get": (C.c_int, [VP, VP, C.c_size_t]),
     "gnp_params_set": (C.c_int, [VP, VP, C.c_size_t]),
+    "gnp_params_set_device": (C.c_int, [VP, VP, C.c_size_t, VP]),
     "gnp_apply": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, VP]),
     "fgmres_solve": (C.c_int, [VP, VP, VP, VP, C.c_int, C.c_double, C.c_int, C.c_int, VP,
                                C.POINTER(SolveInfo), VP]),
+    "gnp_train": (C.c_int, [VP, C.POINTER(TrainOpts), VP, VP, C.POINTER(C.c_int), VP]),
+    "gnp_loss_grad": (C.c_int, [VP, VP, C.c_int, C.c_int, F64P, VP, VP]),
+    "gnp_forward_save": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, VP]),
+    "gnp_backward": (C.c_int, [VP, VP, VP, VP]),
 }
 
 _lib = None

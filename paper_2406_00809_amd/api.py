@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import GNP_BF16, GNP_F32, GNP_F64, GNPError, SolveInfo, check
+from ._lib import GNP_BF16, GNP_F32, GNP_F64, GNPError, SolveInfo, TrainOpts, check
 
 PREC = {"f64": GNP_F64, "f32": GNP_F32, "bf16": GNP_BF16,
         GNP_F64: GNP_F64, GNP_F32: GNP_F32, GNP_BF16: GNP_BF16}
@@ -135,6 +135,32 @@ class Model:
                                     _dev_ptr(z, dt, self.system.n * nrhs, "z"), nrhs, p,
                                     _stream(stream)))
         return z
+
+    def train(self, steps: int, batch: int, lr: float = 1e-3, seed: int = 2, prec="f32",
+              x_fixed: torch.Tensor | None = None, betas=(0.9, 0.999), eps: float = 1e-8,
+              stream=None):
+        """gnp_train: returns (loss history ndarray, best step)."""
+        o = TrainOpts(int(steps), int(batch), float(lr), float(betas[0]), float(betas[1]),
+                      float(eps), int(seed), PREC[prec])
+        hist = np.empty(steps)
+        best = C.c_int(-1)
+        xf = None
+        if x_fixed is not None:
+            xf = _dev_ptr(x_fixed, torch.float64, self.system.n * batch, "x_fixed")
+        check(_lib.load().gnp_train(self._h, C.byref(o), xf, hist.ctypes.data_as(C.c_void_p),
+                                    C.byref(best), _stream(stream)))
+        return hist, best.value
+
+    def loss_grad(self, b: torch.Tensor, prec="f64", stream=None):
+        """gnp_loss_grad on b ([n] or [n, nrhs], float64 device)."""
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        loss = C.c_double()
+        g = np.empty(self.nparams)
+        check(_lib.load().gnp_loss_grad(self._h, _dev_ptr(b, torch.float64,
+                                                          self.system.n * nrhs, "b"),
+                                        nrhs, PREC[prec], C.byref(loss),
+                                        g.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return loss.value, g
 
     def close(self):
         if getattr(self, "_h", None):

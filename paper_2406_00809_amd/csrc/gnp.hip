@@ -73,6 +73,8 @@ static int64_t colnorm_chunk(int64_t n) {
     return c < 512 ? 512 : c;
 }
 
+int colnorm_blocks(int64_t n) { return grid_for(n, (int)colnorm_chunk(n)); }
+
 template <typename IN>
 __global__ __launch_bounds__(BLOCK) void k_colnorm(int64_t n, int B, int64_t chunk,
                                                    const IN *__restrict__ v, double *partial,
@@ -236,6 +238,7 @@ static void model_free(gnp_model *m) {
                     m->ws.tau, m->ws.partial, m->ws.counter};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    train_ctx_free(m->train_ctx);
     delete m;
 }
 
@@ -307,6 +310,17 @@ gnp_status gnp_params_set(gnp_model *m, const double *buf, size_t count) {
     GNP_HIP(hipMemcpy(m->theta64, buf, sizeof(double) * m->np, hipMemcpyHostToDevice));
     GNP_TRY(model_repack(m, nullptr));
     GNP_HIP(hipStreamSynchronize(nullptr));
+    return GNP_OK;
+}
+
+gnp_status gnp_params_set_device(gnp_model *m, const double *buf_dev, size_t count,
+                                 void *hip_stream) {
+    if (!m || !buf_dev) return fail(GNP_EINVAL, "null argument");
+    if (count != (size_t)m->np) return fail(GNP_EINVAL, "count must equal the parameter count");
+    hipStream_t st = (hipStream_t)hip_stream;
+    GNP_HIP(hipMemcpyAsync(m->theta64, buf_dev, sizeof(double) * m->np, hipMemcpyDeviceToDevice,
+                           st));
+    GNP_TRY(model_repack(m, st));
     return GNP_OK;
 }
 

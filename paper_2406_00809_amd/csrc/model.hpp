@@ -77,15 +77,21 @@ struct gnp_model {
     gnp::ParamOffsets po;
     gnp::PackOffsets pb, pf;
     gnp::ApplyWorkspace ws;
+    void *train_ctx = nullptr;     // training workspace (train.hip)
 };
 
 namespace gnp {
+
+void train_ctx_free(void *p);
 
 // Repack the fragment layouts and float32 copy from theta64 (stream-ordered).
 gnp_status model_repack(gnp_model *m, hipStream_t st);
 
 // Make sure the apply workspace can hold nrhs right-hand sides.
 gnp_status model_workspace(gnp_model *m, int nrhs);
+
+// Number of blocks (and partials per column) of launch_colnorm for n rows.
+int colnorm_blocks(int64_t n);
 
 // Column norms of v ([n][nrhs], float or double) into tau triples
 // (tau, sqrt(n)/tau, tau/sqrt(n)) at tau_out[3*k .. 3*k+2].
