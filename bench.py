@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark: GNP-preconditioned FGMRES solves per second to rtol 1e-8.
+
+Workload (one GPU): 3D 7-point convection-diffusion on a 64^3 grid
+(n = 262 144, nnz = 1 810 432, Peclet 10, first-order upwind), prescaled by
+gamma; b = A * ones (the paper's ground truth x = 1, x0 = 0).  Network: L = 8
+Res-GCONV layers, d = 32, MLP hidden 64, trained on the device before the
+timed region (Adam lr 1e-3, batch 32 fresh x ~ N(0, I), b = A x, l1 loss,
+best-loss model kept).  Solve: FGMRES(30) with the network as right
+preconditioner, float64 Arnoldi dots/norms, Givens and true residual,
+float32 SpMV and basis, network in bf16 on MFMA (and float32 for
+comparison).  One step = one whole solve from x0 = 0 to rtol 1e-8.
+
+Prints one JSON line (see the contract in the design doc).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), p))
+
+
+def cpu_baseline(A, th, arch, gpu_iters, sample_iters):
+    """The oracle (FP64 C, OpenMP) on the same system, weights and b: the
+    first `sample_iters` Arnoldi steps of the same FGMRES(30) solve, timed on
+    the host, scaled to solves/s with the GPU's iterations per solve."""
+    import numpy as np
+    import oracle as O
+    S = O.System(A)
+    b = O.spmm(S.A, np.ones(S.n))
+    t0 = time.perf_counter()
+    r = O.fgmres(S, b, 30, 1e-8, sample_iters, M="gnp", theta=th, arch=arch, ortho=O.CGS2)
+    dt = time.perf_counter() - t0
+    its = max(1, r["info"]["iters"])
+    per_iter = dt / its
+    return {
+        "value": 1.0 / (per_iter * gpu_iters),
+        "unit": "solves/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"first {its} Arnoldi steps of the same GNP-FGMRES(30) solve in FP64 "
+                   f"({dt:.1f} s, {per_iter:.3f} s/step), scaled by {gpu_iters} steps/solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--grid", type=int, default=64)
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--maxiters", type=int, default=3000)
+    ap.add_argument("--cpu-sample-iters", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--allow-nonconverged", action="store_true",
+                    help="report instead of failing when a timed solve does not converge")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the float32-network comparison solves")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2406_00809_amd import api
+    from paper_2406_00809_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    L, d, h, m = 8, 32, 64, 30
+    N = args.grid
+    A = I.convdiff3d(N, 10.0)
+    S = api.System(A)
+    th0 = I.init_params(L, d, h, 12)
+    M = api.Model(S, L, d, h, th0)
+    log(f"system n={S.n} nnz={S.nnz} gamma={S.gamma_input:.6f}")
+
+    # ---- setup (untimed): train the preconditioner on the device
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, best = M.train(args.train_steps, 32, lr=1e-3, seed=2, prec="f32")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"trained {args.train_steps} steps in {train_s:.1f}s "
+        f"({1e3 * train_s / args.train_steps:.1f} ms/step); loss {hist[0]:.4f} -> "
+        f"{hist[best]:.4f} (best step {best})")
+    th = M.get_params()
+
+    ones = torch.ones(S.n, dtype=torch.float64, device=dev)
+    b = S.spmv(ones, prec="f64")
+    x = torch.zeros(S.n, dtype=torch.float64, device=dev)
+
+    def solve(prec):
+        x.zero_()
+        return api.fgmres_solve(S, b, M, x=x, m=m, rtol=1e-8, maxiters=args.maxiters,
+                                prec=prec, want_hist=False)
+
+    for _ in range(args.warmup):
+        _, info, _ = solve(args.prec)
+    torch.cuda.synchronize()
+    lat = []
+    iters = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        _, info, _ = solve(args.prec)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+        iters.append(info["iters"])
+        if not args.allow_nonconverged:
+            assert info["converged"] == 1, info
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    xs = x.cpu().numpy()
+    Ad = A.to_scipy() / S.gamma_input
+    bh = Ad @ np.ones(S.n)
+    true_res = float(np.linalg.norm(bh - Ad @ xs) / np.linalg.norm(bh))
+    err_x = float(np.linalg.norm(xs - 1.0) / np.sqrt(S.n))
+    value = args.steps / elapsed
+    log(f"{args.prec}: {value:.3f} solves/s, {iters[0]} its/solve, true rel res {true_res:.2e}")
+
+    # ---- comparison: float32 network (same weights), and unpreconditioned GMRES
+    extra = {}
+    if not args.no_compare:
+        for p in (["f32"] if args.prec != "f32" else []):
+            solve(p)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, inf2, _ = solve(p)
+            torch.cuda.synchronize()
+            extra[f"{p}_network"] = {"solves_per_s": 1.0 / (time.perf_counter() - t1),
+                                     "iters": inf2["iters"],
+                                     "rel_res_true": inf2["rel_res_true"]}
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, inf3, _ = api.fgmres_solve(S, b, None, x=x, m=m, rtol=1e-8, maxiters=args.maxiters,
+                                      prec="f32", want_hist=False)
+        torch.cuda.synchronize()
+        extra["no_preconditioner"] = {"solves_per_s": 1.0 / (time.perf_counter() - t1),
+                                      "iters": inf3["iters"],
+                                      "rel_res_true": inf3["rel_res_true"]}
+
+    # ---- dominant kernel: one Res-GCONV layer, same launch configuration
+    lay_ms = M.time_layer(nrhs=1, prec=args.prec, reps=200)
+    s_act = {"bf16": 2, "f32": 4, "f64": 8}[args.prec]
+    s_val = 8 if args.prec == "f64" else 4
+    layer_bytes = (s_val + 4) * S.nnz + 4 * (S.n + 1) + 2 * S.n * d * s_act
+    achieved = layer_bytes / (lay_ms * 1e-3) / 1e9
+    # SpMV (float32): 8 nnz + 4 (n+1) + 8 n bytes
+    xv = torch.randn(S.n, dtype=torch.float32, device=dev)
+    yv = torch.empty_like(xv)
+    spmv_ms = S.time_spmv(xv, yv, prec="f32", reps=200)
+    spmv_bytes = 8 * S.nnz + 4 * (S.n + 1) + 8 * S.n
+    spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        cpu = cpu_baseline(A, th, (L, d, h), iters[0], args.cpu_sample_iters)
+
+    out = {
+        "metric": "GNP-FGMRES solves/s to rtol 1e-8",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": f"convdiff3d_{N}^3_Pe10_upwind (n={S.n}, nnz={S.nnz}), b=A*1, x0=0; "
+                        f"GNP L={L} d={d} h={h} trained {args.train_steps} Adam steps batch 32; "
+                        f"FGMRES({m}) rtol 1e-8, fp64 Arnoldi/Givens/true residual, fp32 SpMV",
+            "iters_per_solve": iters[0],
+            "rel_res_true": true_res,
+            "rms_error_vs_x_ones": err_x,
+            "latency_p50_ms": 1e3 * percentile(lat, 50),
+            "latency_p99_ms": 1e3 * percentile(lat, 99),
+            "train_s": train_s,
+            "train_ms_per_step": 1e3 * train_s / args.train_steps,
+            "train_loss_first_best": [float(hist[0]), float(hist[best])],
+            "spmv_f32_GBps": spmv_gbs,
+            "spmv_f32_us": 1e3 * spmv_ms,
+            **extra,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"k_layer<{args.prec}> (fused CSR SpMM + MFMA [X|AX][U;W] + ReLU)",
+            "achieved": achieved,
+            "peak": 8000.0,
+            "unit": "GB/s",
+            "frac": achieved / 8000.0,
+            "traffic": None,
+            "avg_us": 1e3 * lay_ms,
+            "algorithmic_bytes": layer_bytes,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

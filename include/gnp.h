@@ -168,7 +168,7 @@ typedef struct {
  * hist[i] = estimated relative residual after Arnoldi step i; entries past
  * info.iters are left untouched.
  * b = 0 gives x = 0, iters = 0, converged = 1.
- * Errors: GNP_EINVAL for m < 1, m > 256, rtol <= 0, maxiters < 1, a model of
+ * Errors: GNP_EINVAL for m < 1, m > 255, rtol <= 0, maxiters < 1, a model of
  * another system or a bad precision; GNP_ENUMERIC when b, the residual, a
  * norm or a Hessenberg entry becomes non-finite. */
 GNP_API gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const double *b_dev,
@@ -228,6 +228,24 @@ GNP_API gnp_status gnp_forward_save(gnp_model *model, const void *b_dev, void *z
  * device, [nparams]).  Errors: GNP_EINVAL without a saved forward. */
 GNP_API gnp_status gnp_backward(gnp_model *model, const void *dz_dev, double *dparams_dev,
                                 void *hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement helpers                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Mean duration (ms) of one launch of the Res-GCONV layer kernel (Eq. (5)),
+ * in the launch configuration of gnp_apply / fgmres_solve for nrhs
+ * right-hand sides and precision prec: `reps` back-to-back launches on
+ * hip_stream between two hipEvents recorded on that stream.  Operates on the
+ * model's apply workspace (run gnp_apply with the same nrhs first so that it
+ * holds real activations).  Synchronises the stream. */
+GNP_API gnp_status gnp_time_layer(gnp_model *model, int nrhs, gnp_precision prec, int reps,
+                                  double *ms_per_launch, void *hip_stream);
+
+/* Mean duration (ms) of one gnp_spmv launch (y = A x), measured the same way. */
+GNP_API gnp_status gnp_time_spmv(const gnp_system *sys, const void *x_dev, void *y_dev,
+                                 gnp_precision prec, int reps, double *ms_per_launch,
+                                 void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -46,6 +46,7 @@ def lib():
                 os.path.join(os.path.dirname(LIB), "oracle.c")):
             build()
         L = C.CDLL(LIB)
+        L.or_num_threads.restype = C.c_int
         L.or_spmm.argtypes = [C.c_int64, I32P, I32P, F64P, C.c_int, F64P, F64P]
         L.or_gamma.argtypes = [C.c_int64, I32P, I32P, F64P]
         L.or_gamma.restype = C.c_double
@@ -84,6 +85,10 @@ def _ptr(a):
 
 def _c64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 # --- CSR ---------------------------------------------------------------------

@@ -41,6 +41,20 @@
 
 #define OR_API __attribute__((visibility("default")))
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+OR_API int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sparse matrix basics                                                     */
 /* ------------------------------------------------------------------------ */

@@ -63,6 +63,8 @@ SIGNATURES = {
     "gnp_loss_grad": (C.c_int, [VP, VP, C.c_int, C.c_int, F64P, VP, VP]),
     "gnp_forward_save": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, VP]),
     "gnp_backward": (C.c_int, [VP, VP, VP, VP]),
+    "gnp_time_layer": (C.c_int, [VP, C.c_int, C.c_int, C.c_int, F64P, VP]),
+    "gnp_time_spmv": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, F64P, VP]),
 }
 
 _lib = None

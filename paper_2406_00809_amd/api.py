@@ -86,6 +86,16 @@ class System:
                                    _dev_ptr(y, dt, self.n, "y"), p, _stream(stream)))
         return y
 
+    def time_spmv(self, x: torch.Tensor, y: torch.Tensor, prec="f32", reps=50, stream=None):
+        """Mean ms per SpMV launch (HIP events on the launch stream)."""
+        p = PREC[prec]
+        dt = KDTYPE[p]
+        ms = C.c_double()
+        check(_lib.load().gnp_time_spmv(self._h, _dev_ptr(x, dt, self.n, "x"),
+                                        _dev_ptr(y, dt, self.n, "y"), p, int(reps),
+                                        C.byref(ms), _stream(stream)))
+        return ms.value
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.load().gnp_system_destroy(self._h)
@@ -150,6 +160,13 @@ class Model:
         check(_lib.load().gnp_train(self._h, C.byref(o), xf, hist.ctypes.data_as(C.c_void_p),
                                     C.byref(best), _stream(stream)))
         return hist, best.value
+
+    def time_layer(self, nrhs=1, prec="bf16", reps=50, stream=None):
+        """Mean ms per Res-GCONV layer launch (HIP events on the launch stream)."""
+        ms = C.c_double()
+        check(_lib.load().gnp_time_layer(self._h, int(nrhs), PREC[prec], int(reps), C.byref(ms),
+                                         _stream(stream)))
+        return ms.value
 
     def loss_grad(self, b: torch.Tensor, prec="f64", stream=None):
         """gnp_loss_grad on b ([n] or [n, nrhs], float64 device)."""

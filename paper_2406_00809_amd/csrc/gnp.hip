@@ -232,6 +232,42 @@ gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void 
     return GNP_OK;
 }
 
+// One Res-GCONV layer launch, exactly as in the forward sequence (nrhs
+// right-hand sides on the apply workspace, layer `l`, non-final variant).
+template <typename G, int D, int H>
+static void layer_once(gnp_model *m, int nrhs, int l, hipStream_t st) {
+    gnp_system *s = m->sys;
+    const int64_t rows = s->n * (int64_t)nrhs;
+    const int grid = grid_for(rows, 64);
+    const void *wc;
+    const typename Act<G>::vt *ahat;
+    const typename Act<G>::acc *vec;
+    if constexpr (sizeof(G) == 8) {
+        wc = m->theta64 + m->po.U0 + (int64_t)l * 2 * D * D;
+        ahat = (const typename Act<G>::vt *)s->ahat64;
+        vec = (const typename Act<G>::acc *)m->theta64;
+    } else if constexpr (sizeof(G) == 4) {
+        wc = m->pk_f32 + m->pf.Wcat0 + l * m->pf.Wcat_stride;
+        ahat = (const typename Act<G>::vt *)s->ahat32;
+        vec = (const typename Act<G>::acc *)m->theta32;
+    } else {
+        wc = m->pk_bf16 + m->pb.Wcat0 + l * m->pb.Wcat_stride;
+        ahat = (const typename Act<G>::vt *)s->ahat32;
+        vec = (const typename Act<G>::acc *)m->theta32;
+    }
+    hipLaunchKernelGGL((k_layer<G, D, H, false, float>), dim3(grid), dim3(BLOCK), 0, st, rows,
+                       nrhs, s->rp, s->ci, ahat, (const G *)m->ws.act[0], (G *)m->ws.act[1], wc,
+                       (const void *)nullptr, vec, m->po.c3, m->po.W4, m->po.c4,
+                       (const double *)m->ws.tau, (float *)nullptr, (const int *)nullptr);
+}
+
+template <int D, int H>
+static void layer_once_prec(gnp_model *m, int nrhs, gnp_precision prec, hipStream_t st) {
+    if (prec == GNP_F64) layer_once<double, D, H>(m, nrhs, 0, st);
+    else if (prec == GNP_F32) layer_once<float, D, H>(m, nrhs, 0, st);
+    else layer_once<uint16_t, D, H>(m, nrhs, 0, st);
+}
+
 static void model_free(gnp_model *m) {
     if (!m) return;
     void *ptrs[] = {m->theta64, m->theta32, m->pk_bf16, m->pk_f32, m->ws.act[0], m->ws.act[1],
@@ -321,6 +357,33 @@ gnp_status gnp_params_set_device(gnp_model *m, const double *buf_dev, size_t cou
     GNP_HIP(hipMemcpyAsync(m->theta64, buf_dev, sizeof(double) * m->np, hipMemcpyDeviceToDevice,
                            st));
     GNP_TRY(model_repack(m, st));
+    return GNP_OK;
+}
+
+gnp_status gnp_time_layer(gnp_model *m, int nrhs, gnp_precision prec, int reps,
+                          double *ms_per_launch, void *hip_stream) {
+    if (!m || !ms_per_launch) return fail(GNP_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > BLOCK || reps < 1) return fail(GNP_EINVAL, "bad nrhs or reps");
+    if (!valid_precision(prec)) return fail(GNP_EINVAL, "bad precision");
+    hipStream_t st = (hipStream_t)hip_stream;
+    GNP_TRY(model_workspace(m, nrhs));
+    hipEvent_t e0, e1;
+    GNP_HIP(hipEventCreate(&e0));
+    GNP_HIP(hipEventCreate(&e1));
+    auto once = [&]() {
+        if (m->d == 16) layer_once_prec<16, 32>(m, nrhs, prec, st);
+        else layer_once_prec<32, 64>(m, nrhs, prec, st);
+    };
+    once();  // warm the instruction cache and the workspace
+    GNP_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) once();
+    GNP_HIP(hipEventRecord(e1, st));
+    GNP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GNP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = (double)ms / reps;
     return GNP_OK;
 }
 

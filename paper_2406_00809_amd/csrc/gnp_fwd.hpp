@@ -67,6 +67,16 @@ __device__ __forceinline__ void store_feats(G *p, const typename Act<G>::acc (&i
 
 template <typename T> __device__ __forceinline__ T relu(T x) { return x > (T)0 ? x : (T)0; }
 
+// Every LDS region of these kernels belongs to one wavefront, and a
+// wavefront's LDS operations execute in order, so a wavefront-scope fence
+// (ordering for the compiler) replaces a block barrier between the write and
+// read phases; the four wavefronts of a block never wait for each other.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p) {
     uint4 u = *reinterpret_cast<const uint4 *>(p);
     return __builtin_bit_cast(bf16x8, u);
@@ -110,6 +120,7 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
         for (int e = 0; e < D / 4; ++e) out[e] += c2[q * (D / 4) + e];
         store_feats<G, D / 4>(E + r * D + q * (D / 4), out);
     } else {
+        __shared__ __attribute__((aligned(16))) G Es[BLOCK / WAVE][16][D + 8];
         const int64_t ra = r0 + lane % 16;
         const float u = ra < rows ? (float)(tau[3 * (ra % B) + 1] * (double)v[ra]) : 0.f;
         f32x4 o[D / 16];
@@ -144,15 +155,22 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
                         o[nt], 0, 0, 0);
             }
         }
+        // stage the 16 x D output tile in LDS, then 16-byte coalesced stores
 #pragma unroll
         for (int nt = 0; nt < D / 16; ++nt) {
             const int col = nt * 16 + lane % 16;
             const float cb = c2[col];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t r = r0 + 4 * (lane / 16) + j;
-                if (r < rows) E[r * D + col] = Act<G>::put(o[nt][j] + cb);
-            }
+            for (int j = 0; j < 4; ++j) Es[wv][4 * (lane / 16) + j][col] = Act<G>::put(o[nt][j] + cb);
+        }
+        wave_lds_sync();
+        const int rl = lane / 4, q = lane % 4;
+        const int64_t r = r0 + rl;
+        if (r < rows) {
+            typename Act<G>::acc ov[D / 4];
+#pragma unroll
+            for (int e = 0; e < D / 4; ++e) ov[e] = Act<G>::get(Es[wv][rl][q * (D / 4) + e]);
+            store_feats<G, D / 4>(E + r * D + q * (D / 4), ov);
         }
     }
 }
@@ -178,6 +196,30 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     const int64_t r0 = ((int64_t)blockIdx.x * (BLOCK / WAVE) + wv) * 16;
 
+    // ---- stage the tile's slice of the CSR arrays (rows r0 .. r0+15 touch
+    // nodes ifirst .. ilast, whose nonzeros are contiguous) in LDS
+    using vt_t = typename Act<G>::vt;
+    constexpr int CAP = 256;
+    __shared__ int32_t sRp[BLOCK / WAVE][17];
+    __shared__ int32_t sCi[BLOCK / WAVE][CAP];
+    __shared__ vt_t sVa[BLOCK / WAVE][CAP];
+    const bool live = r0 < rows;
+    const int64_t rlast = (r0 + 15 < rows) ? r0 + 15 : rows - 1;
+    const int64_t ifirst = live ? ((B == 1) ? r0 : r0 / B) : 0;
+    const int64_t ilast = live ? ((B == 1) ? rlast : rlast / B) : 0;
+    const int32_t kbeg = live ? rp[ifirst] : 0;
+    const int32_t cnt = live ? rp[ilast + 1] - kbeg : 0;
+    const bool staged = cnt <= CAP;
+    if (live && lane <= (int)(ilast - ifirst)) sRp[wv][lane] = rp[ifirst + lane] - kbeg;
+    if (live && lane == 0) sRp[wv][ilast - ifirst + 1] = cnt;
+    if (live && staged) {
+        for (int t2 = lane; t2 < cnt; t2 += WAVE) {
+            sCi[wv][t2] = ci[kbeg + t2];
+            sVa[wv][t2] = ahat[kbeg + t2];
+        }
+    }
+    wave_lds_sync();
+
     // ---- phase 1: gather T = A-hat X and the row's own X into LDS
     {
         const int rl = lane / 4, q = lane % 4;
@@ -188,16 +230,43 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
         if (r < rows) {
             const int64_t i = (B == 1) ? r : r / B;
             const int b = (int)(r - i * B);
-            const int32_t ke = rp[i + 1];
-            for (int32_t k = rp[i]; k < ke; ++k) {
-                const int64_t c = ci[k];
-                const acc_t a = (acc_t)ahat[k];
-                acc_t xv[D / 4];
-                load_feats<G, D / 4>(X + (c * B + b) * D + q * (D / 4), xv);
-#pragma unroll
-                for (int e = 0; e < D / 4; ++e) t[e] += a * xv[e];
-            }
+            const int li = (int)(i - ifirst);
+            const int32_t ks = sRp[wv][li], ke = sRp[wv][li + 1];
             load_feats<G, D / 4>(X + r * D + q * (D / 4), s);
+            if (staged) {
+                // neighbours in batches of NB: all gathers issued before the FMAs;
+                // short rows re-load a valid neighbour with weight 0
+                constexpr int NB = sizeof(G) == 2 ? 8 : 4;
+                constexpr int CB = (D / 4) * (int)sizeof(G);
+                for (int32_t k0 = ks; k0 < ke; k0 += NB) {
+                    Chunk<CB> raw[NB];  // packed until the FMAs (register economy)
+                    acc_t av[NB];
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const bool ok = k0 + u < ke;
+                        const int32_t kk = ok ? k0 + u : ks;
+                        const int64_t c = sCi[wv][kk];
+                        av[u] = ok ? (acc_t)sVa[wv][kk] : (acc_t)0;
+                        raw[u] = *reinterpret_cast<const Chunk<CB> *>(X + (c * B + b) * D +
+                                                                      q * (D / 4));
+                    }
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const G *e8 = reinterpret_cast<const G *>(&raw[u]);
+#pragma unroll
+                        for (int e = 0; e < D / 4; ++e) t[e] += av[u] * Act<G>::get(e8[e]);
+                    }
+                }
+            } else {
+                for (int32_t k = kbeg + ks; k < kbeg + ke; ++k) {
+                    const int64_t c = ci[k];
+                    const acc_t a = (acc_t)ahat[k];
+                    acc_t xv[D / 4];
+                    load_feats<G, D / 4>(X + (c * B + b) * D + q * (D / 4), xv);
+#pragma unroll
+                    for (int e = 0; e < D / 4; ++e) t[e] += a * xv[e];
+                }
+            }
         }
 #pragma unroll
         for (int e = 0; e < D / 4; ++e) {
@@ -205,7 +274,7 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
             As[wv][rl][D + q * (D / 4) + e] = Act<G>::put(t[e]);
         }
     }
-    __syncthreads();
+    wave_lds_sync();
 
     if constexpr (sizeof(G) == 8) {
         // ---- FP64 VALU path
@@ -223,10 +292,10 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
         if constexpr (!DEC) {
             if (r < rows) store_feats<G, D / 4>(Y + r * D + q * (D / 4), y);
         } else {
-            __syncthreads();
+            wave_lds_sync();
 #pragma unroll
             for (int e = 0; e < D / 4; ++e) As[wv][rl][q * (D / 4) + e] = y[e];
-            __syncthreads();
+            wave_lds_sync();
             const double *W3 = (const double *)w3;
             const double *c3 = vec + oc3, *W4 = vec + oW4;
             double part = 0.0;
@@ -271,17 +340,25 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
             }
         }
         if constexpr (!DEC) {
+            wave_lds_sync();  // every lane has read its A fragments
 #pragma unroll
             for (int nt = 0; nt < D / 16; ++nt) {
                 const int col = nt * 16 + lane % 16;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int64_t r = r0 + 4 * (lane / 16) + j;
-                    if (r < rows) Y[r * D + col] = Act<G>::put(relu(o[nt][j]));
-                }
+                for (int j = 0; j < 4; ++j)
+                    As[wv][4 * (lane / 16) + j][col] = Act<G>::put(relu(o[nt][j]));
+            }
+            wave_lds_sync();
+            const int rl = lane / 4, q = lane % 4;
+            const int64_t r = r0 + rl;
+            if (r < rows) {
+                acc_t ov[D / 4];
+#pragma unroll
+                for (int e = 0; e < D / 4; ++e) ov[e] = Act<G>::get(As[wv][rl][q * (D / 4) + e]);
+                store_feats<G, D / 4>(Y + r * D + q * (D / 4), ov);
             }
         } else {
-            __syncthreads();
+            wave_lds_sync();
             constexpr int KP = (sizeof(G) == 2) ? ((D + 31) / 32) * 32 : D;
 #pragma unroll
             for (int nt = 0; nt < D / 16; ++nt) {
@@ -292,7 +369,7 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
                     if constexpr (KP > D) As[wv][4 * (lane / 16) + j][D + col] = Act<G>::put(0.f);
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
             f32x4 hacc[H / 16];
 #pragma unroll
             for (int nt = 0; nt < H / 16; ++nt) hacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};

@@ -3,9 +3,21 @@
 // SpMV w = A z_j, three classical Gram-Schmidt passes (dots; update + dots;
 // update + norm, i.e. CGS applied twice with float64 inner products), the
 // Givens update of the Hessenberg column on the device, and the
-// normalisation v_{j+1} = w / h_{j+1,j} fused with the float64 norm that the
-// next network input needs for its scaling (Eq. (6)).  All reductions are
-// two-stage and deterministic.  The host synchronises once per cycle.
+// normalisation v_{j+1} = w / h_{j+1,j} with the float64 norm that the next
+// network input needs for its scaling (Eq. (6)).
+//
+// Layout: the Arnoldi basis is stored row-interleaved, V[i * MP + k]
+// (MP = m + 1 rounded up to a multiple of 32), so that the j + 1 basis
+// entries of one row sit in one 128-byte line: a Gram-Schmidt pass reads
+// each row once with eight lanes per row (float4 per lane) instead of j + 1
+// separate streams.  The current v_j is also kept contiguous (vcur) as the
+// network input.  Z (network outputs) is column-major: z_j is the SpMV input.
+//
+// Reductions are deterministic: each block writes its partial sums, and a
+// one-block finalize kernel adds the partials in block order (lanes over
+// columns, wavefronts over block subsets, eight independent loads per lane).
+// The host synchronises once per restart cycle; every kernel of a step exits
+// at entry once the device-side control block says the cycle is over.
 #include <math.h>
 #include <string.h>
 
@@ -16,39 +28,108 @@
 
 namespace gnp {
 
-constexpr int CH = 32;  // basis vectors per dot-product chunk
+constexpr int RPP = BLOCK / 8;  // rows per pass in the Gram-Schmidt kernels
+constexpr int MAXCOL = 258;     // columns of a finalize reduction (m + 2)
 
-static int stream_grid(int64_t n) { return grid_for(n, 4 * BLOCK, 2048); }
+static int stream_grid(int64_t n) { return grid_for(n, 4 * BLOCK, 1024); }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_bnorm(int64_t n, const double *__restrict__ b,
-                                                 double rtol, double *partial, unsigned *counter,
-                                                 Ctl *ctl) {
+// one-block finalize helper: out[c] = sum over blk < nblk of
+// partial[blk * stride + c] for c < ncol, fixed summation order.
+// ---------------------------------------------------------------------------
+__device__ void reduce_columns(int nblk, int ncol, const double *__restrict__ partial, int stride,
+                               double *out /* shared, >= ncol */) {
+    __shared__ double sh[BLOCK];
+    const int t = threadIdx.x;
+    if (ncol == 1) {
+        // every thread takes blocks t, t + BLOCK, ... (independent loads)
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int blk0 = t; blk0 < nblk; blk0 += 4 * BLOCK) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int blk = blk0 + u * BLOCK;
+                v[u] = partial[(int64_t)(blk < nblk ? blk : nblk - 1) * stride];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += (blk0 + u * BLOCK < nblk) ? v[u] : 0.0;
+        }
+        const double s = block_sum((a[0] + a[1]) + (a[2] + a[3]), sh);
+        if (t == 0) out[0] = s;
+        __syncthreads();
+        return;
+    }
+    // lanes over columns (CP per chunk), the rest over block subsets; each
+    // thread keeps 16 independent loads in flight per round
+    const int CP = ncol <= 32 ? 32 : 64;
+    const int S = BLOCK / CP;
+    const int cl = t % CP, sub = t / CP;
+    for (int c0 = 0; c0 < ncol; c0 += CP) {
+        const int col = c0 + cl;
+        double a[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u] = 0.0;
+        const int colc = col < ncol ? col : ncol - 1;
+        for (int blk0 = sub * 16; blk0 < nblk; blk0 += S * 16) {
+            // clamped, unconditional loads: all 16 in flight before the adds
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int blk = (blk0 + u < nblk) ? blk0 + u : nblk - 1;
+                v[u] = partial[(int64_t)blk * stride + colc];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) a[u] += (blk0 + u < nblk && col < ncol) ? v[u] : 0.0;
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += a[u];
+        sh[t] = s;
+        __syncthreads();
+        if (t < CP && c0 + t < ncol) {
+            double v = 0.0;
+            for (int q = 0; q < S; ++q) v += sh[q * CP + t];
+            out[c0 + t] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ||b||^2 partials and finalize
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_sumsq(int64_t n, const double *__restrict__ x,
+                                                 double *__restrict__ partial) {
     __shared__ double sh[BLOCK / WAVE];
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * BLOCK)
-        s += b[i] * b[i];
+        s += x[i] * x[i];
     s = block_sum(s, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
-    if (last_block(counter)) {
-        double a = 0.0;
-        for (unsigned k = threadIdx.x; k < gridDim.x; k += BLOCK) a += partial[k];
-        a = block_sum(a, sh);
-        if (threadIdx.x == 0) {
-            ctl->bnorm = sqrt(a);
-            ctl->target = rtol * sqrt(a);
-        }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fin_bnorm(int nblk, const double *partial, double rtol,
+                                                     Ctl *ctl) {
+    __shared__ double res[1];
+    reduce_columns(nblk, 1, partial, 1, res);
+    if (threadIdx.x == 0) {
+        ctl->bnorm = sqrt(res[0]);
+        ctl->target = rtol * sqrt(res[0]);
     }
 }
 
-// r = b - A x (float64 values, float64 x), beta = ||r||, restart bookkeeping
+// ---------------------------------------------------------------------------
+// true residual r = b - A x (float64 values and x), partial ||r||^2
+// ---------------------------------------------------------------------------
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_residual(
-    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const double *__restrict__ val, const double *__restrict__ x, const double *__restrict__ b,
-    double *__restrict__ r, double *partial, unsigned *counter, Ctl *ctl, double *g, double *hist,
-    int initial) {
+__global__ __launch_bounds__(BLOCK) void k_residual(int64_t n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ ci,
+                                                    const double *__restrict__ val,
+                                                    const double *__restrict__ x,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ r,
+                                                    double *__restrict__ partial) {
     __shared__ double sh[BLOCK / WAVE];
     const int lg = threadIdx.x % G;
     double s = 0.0;
@@ -67,45 +148,50 @@ __global__ __launch_bounds__(BLOCK) void k_residual(
     }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
-    if (last_block(counter)) {
-        double a = 0.0;
-        for (unsigned k = threadIdx.x; k < gridDim.x; k += BLOCK) a += partial[k];
-        a = block_sum(a, sh);
-        if (threadIdx.x == 0) {
-            const double beta = sqrt(a);
-            const double rel = beta / ctl->bnorm;
-            ctl->rel_true = rel;
-            ctl->beta = beta;
-            if (initial) {
-                if (hist) hist[0] = rel;
-                ctl->est_rel = rel;
-            }
-            if (!isfinite(beta)) {
-                ctl->nonfinite = 1;
-                ctl->solve_done = 1;
-            } else if (beta <= ctl->target) {
-                ctl->converged = 1;
-                ctl->solve_done = 1;
-            } else if (ctl->it >= ctl->maxiters) {
-                ctl->solve_done = 1;
-            } else if (!initial) {
-                ctl->restarts += 1;
-            }
-            ctl->cycle_done = ctl->solve_done;
-            ctl->kcols = 0;
-            ctl->kuse = 0;
-        }
-        for (int k = threadIdx.x; k <= ctl->m; k += BLOCK) g[k] = (k == 0) ? sqrt(a) : 0.0;
-    }
 }
 
-// v = src / div (div = beta or h_{j+1,j}); tau triple from ||v||_2 of the
-// stored (rounded) v, for the scaling s of the next network input.
-template <typename KT, typename ST>
-__global__ __launch_bounds__(BLOCK) void k_scale_norm(int64_t n, const ST *__restrict__ src,
-                                                      KT *__restrict__ v, double *partial,
-                                                      unsigned *counter, const Ctl *ctl,
-                                                      int use_beta, double *tau) {
+// beta = ||r||; convergence / iteration-limit decision; restart bookkeeping
+__global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *partial, Ctl *ctl,
+                                                        double *g, double *hist, int initial) {
+    __shared__ double res[1];
+    reduce_columns(nblk, 1, partial, 1, res);
+    const double beta = sqrt(res[0]);
+    if (threadIdx.x == 0) {
+        const double rel = beta / ctl->bnorm;
+        ctl->rel_true = rel;
+        ctl->beta = beta;
+        if (initial) {
+            if (hist) hist[0] = rel;
+            ctl->est_rel = rel;
+        }
+        if (!isfinite(beta)) {
+            ctl->nonfinite = 1;
+            ctl->solve_done = 1;
+        } else if (beta <= ctl->target) {
+            ctl->converged = 1;
+            ctl->solve_done = 1;
+        } else if (ctl->it >= ctl->maxiters) {
+            ctl->solve_done = 1;
+        } else if (!initial) {
+            ctl->restarts += 1;
+        }
+        ctl->cycle_done = ctl->solve_done;
+        ctl->kcols = 0;
+        ctl->kuse = 0;
+    }
+    for (int k = threadIdx.x; k <= ctl->m; k += BLOCK) g[k] = (k == 0) ? beta : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// v = src / div into basis column `col` and vcur; partial ||v||^2 of the
+// stored (rounded) values.  div = beta (cycle start) or h_{j+1,j}.
+// ---------------------------------------------------------------------------
+template <typename KT, typename ST, int MP>
+__global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__restrict__ src,
+                                                     KT *__restrict__ V, int col,
+                                                     KT *__restrict__ vcur,
+                                                     double *__restrict__ partial, const Ctl *ctl,
+                                                     int use_beta) {
     if (ctl->cycle_done) return;
     __shared__ double sh[BLOCK / WAVE];
     const double div = use_beta ? ctl->beta : ctl->hnext;
@@ -113,124 +199,202 @@ __global__ __launch_bounds__(BLOCK) void k_scale_norm(int64_t n, const ST *__res
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * BLOCK) {
         const KT t = (KT)((double)src[i] / div);
-        v[i] = t;
+        V[i * MP + col] = t;
+        vcur[i] = t;
         s += (double)t * (double)t;
     }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
-    if (last_block(counter)) {
-        double a = 0.0;
-        for (unsigned k = threadIdx.x; k < gridDim.x; k += BLOCK) a += partial[k];
-        a = block_sum(a, sh);
-        if (threadIdx.x == 0) {
-            const double tv = sqrt(a), sqn = sqrt((double)n);
-            tau[0] = tv;
-            tau[1] = tv > 0.0 ? sqn / tv : 0.0;
-            tau[2] = tv / sqn;
-        }
+}
+
+// tau triple (tau, sqrt(n)/tau, tau/sqrt(n)) of the network input, Eq. (6)
+__global__ __launch_bounds__(BLOCK) void k_fin_tau(int nblk, const double *partial, int64_t n,
+                                                   double *tau, const Ctl *ctl) {
+    if (ctl->cycle_done) return;
+    __shared__ double res[1];
+    reduce_columns(nblk, 1, partial, 1, res);
+    if (threadIdx.x == 0) {
+        const double tv = sqrt(res[0]), sqn = sqrt((double)n);
+        tau[0] = tv;
+        tau[1] = tv > 0.0 ? sqn / tv : 0.0;
+        tau[2] = tv / sqn;
     }
 }
 
-// Block-reduce CH accumulators into partial[blk * stride + base + k].
-__device__ __forceinline__ void block_reduce_chunk(double (&acc)[CH], double *sh, double *dst,
-                                                   int count) {
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        const double v = wave_sum(acc[k]);
-        if (lane == 0) sh[wv * CH + k] = v;
+// ---------------------------------------------------------------------------
+// Gram-Schmidt passes over the interleaved basis (8 lanes per row, lane q
+// owns entries k = 4 (q + 8 u) + e).  MODE 0: dots V_j^T w and ||w||^2.
+// MODE 1: w -= V_j hprev, then dots.  MODE 2: w -= V_j hprev, then ||w||^2.
+// Entries k > j are masked by selection (they may hold an older cycle).
+// ---------------------------------------------------------------------------
+template <typename KT> struct Quad;
+template <> struct Quad<float> {
+    static __device__ __forceinline__ void load_raw(const float *p, float *o) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
     }
-    __syncthreads();
-    if ((int)threadIdx.x < count) {
-        double s = 0.0;
-        for (int q = 0; q < BLOCK / WAVE; ++q) s += sh[q * CH + threadIdx.x];
-        dst[threadIdx.x] = s;
+};
+template <> struct Quad<double> {
+    static __device__ __forceinline__ void load_raw(const double *p, double *o) {
+        const double2 a = *reinterpret_cast<const double2 *>(p);
+        const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
     }
-    __syncthreads();
-}
+};
 
-// Classical Gram-Schmidt pass over V_0..V_j (float64 arithmetic on the
-// stored vectors).  MODE 0: h = V^T w and ||w||^2.  MODE 1: w -= V hprev,
-// then h = V^T w.  MODE 2: w -= V hprev, then ||w||^2 and the Givens update.
-template <typename KT, int MODE>
+template <typename KT, int MP, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, const KT *__restrict__ V,
                                                int j, KT *__restrict__ w,
                                                const double *__restrict__ hprev,
-                                               double *__restrict__ hout, double *partial,
-                                               int pstride, unsigned *counter, Ctl *ctl,
-                                               double *H, double *H0, double *cs, double *sn,
-                                               double *g, double *hist) {
+                                               double *__restrict__ partial, int pstride,
+                                               const Ctl *ctl) {
     if (ctl->cycle_done) return;
-    __shared__ double sh[(BLOCK / WAVE) * CH];
+    constexpr int NU = MP / 32, NA = 4 * NU;
+    const int t = threadIdx.x, q = t % 8, g = t / 8;
     const int64_t i0 = (int64_t)blockIdx.x * rpb;
     const int64_t i1 = (i0 + rpb < n) ? i0 + rpb : n;
+    double acc[NA], hp[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        acc[a] = 0.0;
+        const int k = 4 * (q + 8 * (a / 4)) + a % 4;
+        hp[a] = (MODE >= 1 && k <= j) ? hprev[k] : 0.0;
+    }
     double nrm = 0.0;
-    if (MODE >= 1) {
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
-            double corr = 0.0;
-            for (int k = 0; k <= j; ++k) corr += hprev[k] * (double)V[(int64_t)k * n + i];
-            const KT wi = (KT)((double)w[i] - corr);
-            w[i] = wi;
-            if (MODE == 2) nrm += (double)wi * (double)wi;
+    // every row of the block in one round of loads (rpb = RPP * RU)
+    constexpr int RU0 = (sizeof(KT) == 4 ? 16 : 8) * 32 / MP;
+    constexpr int RU = RU0 < 2 ? 2 : RU0;
+    for (int64_t ib = i0 + g; ib < i1; ib += (int64_t)RPP * RU) {
+        KT v[RU][NA];
+        KT wold[RU];
+#pragma unroll
+        for (int ru = 0; ru < RU; ++ru) {
+            const int64_t i = ib + (int64_t)ru * RPP;
+            const int64_t ic = i < i1 ? i : i1 - 1;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int c = q + 8 * u;
+                if (4 * c <= j) {
+                    Quad<KT>::load_raw(V + ic * MP + 4 * c, &v[ru][4 * u]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[ru][4 * u + e] = (KT)0;
+                }
+            }
+            wold[ru] = w[ic];
+        }
+#pragma unroll
+        for (int ru = 0; ru < RU; ++ru) {
+            const int64_t i = ib + (int64_t)ru * RPP;
+            const bool ok = i < i1;
+            double vv[NA];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const int k = 4 * (q + 8 * (a / 4)) + a % 4;
+                vv[a] = (k <= j) ? (double)v[ru][a] : 0.0;
+            }
+            double wi;
+            if (MODE == 0) {
+                wi = ok ? (double)wold[ru] : 0.0;
+            } else {
+                double corr = 0.0;
+#pragma unroll
+                for (int a = 0; a < NA; ++a) corr += hp[a] * vv[a];
+                corr += __shfl_xor(corr, 1, WAVE);
+                corr += __shfl_xor(corr, 2, WAVE);
+                corr += __shfl_xor(corr, 4, WAVE);
+                const KT wn = (KT)((double)wold[ru] - corr);
+                if (ok && q == 0) w[i] = wn;
+                wi = ok ? (double)wn : 0.0;
+            }
+            if (MODE <= 1) {
+#pragma unroll
+                for (int a = 0; a < NA; ++a) acc[a] += vv[a] * wi;
+            }
+            if (MODE != 1 && q == 0) nrm += wi * wi;
         }
     }
+    __shared__ double sh[BLOCK / WAVE][8 * NA + 1];
+    const int lane = t % WAVE, wv = t / WAVE;
     if (MODE <= 1) {
-        for (int kc = 0; kc <= j; kc += CH) {
-            double acc[CH];
 #pragma unroll
-            for (int k = 0; k < CH; ++k) acc[k] = 0.0;
-            for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
-                const double wi = (double)w[i];
-                if (MODE == 0 && kc == 0) nrm += wi * wi;
-#pragma unroll
-                for (int k = 0; k < CH; ++k)
-                    if (kc + k <= j) acc[k] += (double)V[(int64_t)(kc + k) * n + i] * wi;
-            }
-            const int cnt = std::min(CH, j + 1 - kc);
-            block_reduce_chunk(acc, sh, partial + (int64_t)blockIdx.x * pstride + kc, cnt);
+        for (int a = 0; a < NA; ++a) {
+            double s = acc[a];
+            s += __shfl_xor(s, 8, WAVE);
+            s += __shfl_xor(s, 16, WAVE);
+            s += __shfl_xor(s, 32, WAVE);
+            if (lane < 8) sh[wv][lane * NA + a] = s;
         }
     }
     if (MODE != 1) {
-        const double s = block_sum(nrm, sh);
-        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * pstride + (pstride - 1)] = s;
+        const double s = wave_sum(nrm);
+        if (lane == 0) sh[wv][8 * NA] = s;
     }
-    if (!last_block(counter)) return;
-    // ---- last block: combine partials in block order
+    __syncthreads();
+    double *dst = partial + (int64_t)blockIdx.x * pstride;
     if (MODE <= 1) {
-        for (int t = threadIdx.x; t <= j; t += BLOCK) {
-            double a = 0.0;
-            for (unsigned blk = 0; blk < gridDim.x; ++blk) a += partial[(int64_t)blk * pstride + t];
-            hout[t] = a;
+        for (int k = t; k <= j; k += BLOCK) {
+            const int c = k / 4, e = k % 4, qq = c % 8, u = c / 8;
+            double s = 0.0;
+            for (int w2 = 0; w2 < BLOCK / WAVE; ++w2) s += sh[w2][qq * NA + 4 * u + e];
+            dst[k] = s;
         }
     }
+    if (MODE != 1 && t == 0) {
+        double s = 0.0;
+        for (int w2 = 0; w2 < BLOCK / WAVE; ++w2) s += sh[w2][8 * NA];
+        dst[pstride - 1] = s;
+    }
+}
+
+// dots finalize: hout[0..j] (and ||A z_j|| from the norm slot in MODE 0)
+template <int MODE>
+__global__ __launch_bounds__(BLOCK) void k_fin_dots(int nblk, int j, const double *partial,
+                                                    int pstride, double *hout, Ctl *ctl) {
+    if (ctl->cycle_done) return;
+    __shared__ double res[MAXCOL];
+    reduce_columns(nblk, j + 1, partial, pstride, res);
+    for (int k = threadIdx.x; k <= j; k += BLOCK) hout[k] = res[k];
     if (MODE == 0) {
-        if (threadIdx.x == 0) {
-            double a = 0.0;
-            for (unsigned blk = 0; blk < gridDim.x; ++blk)
-                a += partial[(int64_t)blk * pstride + (pstride - 1)];
-            ctl->wnorm0 = sqrt(a);
+        reduce_columns(nblk, 1, partial + (pstride - 1), pstride, res);
+        if (threadIdx.x == 0) ctl->wnorm0 = sqrt(res[0]);
+    }
+}
+
+// h_{j+1,j} = ||w||, column j of H-bar = h1 + h2, Givens rotation, residual
+// estimate, end-of-cycle decision.  Inputs are staged in LDS by all threads
+// (one round of loads), the sequential rotation runs in one thread on LDS.
+__global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const double *partial,
+                                                      int pstride, const double *h1,
+                                                      const double *h2, Ctl *ctl, double *H,
+                                                      double *H0, double *cs, double *sn,
+                                                      double *g, double *hist) {
+    if (ctl->cycle_done) return;
+    __shared__ double res[1];
+    __shared__ double col[MAXCOL], scs[MAXCOL], ssn[MAXCOL];
+    __shared__ double gj_s;
+    const int m = ctl->m;
+    for (int i = threadIdx.x; i <= j; i += BLOCK) {
+        col[i] = h1[i] + h2[i];
+        if (i < j) {
+            scs[i] = cs[i];
+            ssn[i] = sn[i];
         }
     }
-    if (MODE == 2 && threadIdx.x == 0) {
-        double a = 0.0;
-        for (unsigned blk = 0; blk < gridDim.x; ++blk)
-            a += partial[(int64_t)blk * pstride + (pstride - 1)];
-        const double hn = sqrt(a);
-        const int m = ctl->m;
-        // column j of H-bar: h1 + h2 (hout holds h1, hprev holds h2), then ||w||
-        for (int i = 0; i <= j; ++i) {
-            const double v = hout[i] + hprev[i];
-            H0[(int64_t)i * m + j] = v;
-            H[(int64_t)i * m + j] = v;
-        }
+    if (threadIdx.x == 0) gj_s = g[j];
+    reduce_columns(nblk, 1, partial + (pstride - 1), pstride, res);  // ends with a barrier
+    const double hn = sqrt(res[0]);
+    for (int i = threadIdx.x; i <= j; i += BLOCK) H0[(int64_t)i * m + j] = col[i];
+    if (threadIdx.x == 0) {
         H0[(int64_t)(j + 1) * m + j] = hn;
+        col[j + 1] = hn;
         // previous rotations (Saad 2003, Sec. 6.5.3), then a new one
         for (int i = 0; i < j; ++i) {
-            const double a0 = H[(int64_t)i * m + j], b0 = H[(int64_t)(i + 1) * m + j];
-            H[(int64_t)i * m + j] = cs[i] * a0 + sn[i] * b0;
-            H[(int64_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * b0;
+            const double a0 = col[i], b0 = col[i + 1];
+            col[i] = scs[i] * a0 + ssn[i] * b0;
+            col[i + 1] = -ssn[i] * a0 + scs[i] * b0;
         }
-        const double a0 = H[(int64_t)j * m + j];
+        const double a0 = col[j];
         const double rho = hypot(a0, hn);
         double c = 1.0, s = 0.0;
         if (rho != 0.0) {
@@ -239,12 +403,12 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, const KT 
         }
         cs[j] = c;
         sn[j] = s;
-        H[(int64_t)j * m + j] = rho;
-        H[(int64_t)(j + 1) * m + j] = 0.0;
-        const double gj = g[j];
+        col[j] = rho;
+        col[j + 1] = 0.0;
+        const double gj = gj_s;
         g[j + 1] = -s * gj;
         g[j] = c * gj;
-        const double est = fabs(g[j + 1]);
+        const double est = fabs(s * gj);
         ctl->est = est;
         ctl->est_rel = est / ctl->bnorm;
         ctl->it += 1;
@@ -262,24 +426,56 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, const KT 
             if (est <= ctl->target || j + 1 >= m || ctl->it >= ctl->maxiters) ctl->cycle_done = 1;
         }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += BLOCK) H[(int64_t)i * m + j] = col[i];
 }
 
-// y = R^{-1} g on the leading columns with nonzero pivots (one thread)
-__global__ void k_backsolve(Ctl *ctl, const double *H, const double *g, double *y) {
-    if (threadIdx.x != 0) return;
+// y = R^{-1} g on the leading columns with nonzero pivots: the triangle and g
+// are staged in LDS by all threads, then one thread substitutes backwards.
+__global__ __launch_bounds__(BLOCK) void k_backsolve(Ctl *ctl, const double *H, const double *g,
+                                                     double *y) {
+    __shared__ double R[64 * 64];
+    __shared__ double gs[64], ys[64];
+    __shared__ int kk_s;
     const int m = ctl->m;
-    int kk = ctl->kcols;
-    while (kk > 0 && H[(int64_t)(kk - 1) * m + (kk - 1)] == 0.0) --kk;
-    for (int i = kk - 1; i >= 0; --i) {
-        double acc = g[i];
-        for (int q = i + 1; q < kk; ++q) acc -= H[(int64_t)i * m + q] * y[q];
-        y[i] = acc / H[(int64_t)i * m + i];
+    const int kc = ctl->kcols;
+    const bool staged = kc <= 64;
+    if (staged) {
+        for (int e = threadIdx.x; e < kc * kc; e += BLOCK) {
+            const int i = e / kc, q = e % kc;
+            R[i * 64 + q] = (q >= i) ? H[(int64_t)i * m + q] : 0.0;
+        }
+        for (int i = threadIdx.x; i < kc; i += BLOCK) gs[i] = g[i];
     }
-    ctl->kuse = kk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int kk = kc;
+        if (staged) {
+            while (kk > 0 && R[(kk - 1) * 64 + (kk - 1)] == 0.0) --kk;
+            for (int i = kk - 1; i >= 0; --i) {
+                double acc = gs[i];
+                for (int q = i + 1; q < kk; ++q) acc -= R[i * 64 + q] * ys[q];
+                ys[i] = acc / R[i * 64 + i];
+            }
+        } else {
+            while (kk > 0 && H[(int64_t)(kk - 1) * m + (kk - 1)] == 0.0) --kk;
+            for (int i = kk - 1; i >= 0; --i) {
+                double acc = g[i];
+                for (int q = i + 1; q < kk; ++q) acc -= H[(int64_t)i * m + q] * y[q];
+                y[i] = acc / H[(int64_t)i * m + i];
+            }
+        }
+        kk_s = kk;
+        ctl->kuse = kk;
+    }
+    __syncthreads();
+    if (staged)
+        for (int i = threadIdx.x; i < kk_s; i += BLOCK) y[i] = ys[i];
 }
 
-// x += Z y  (float64 accumulation)
-template <typename KT>
+// x += Z y (float64 accumulation).  Z column-major (network outputs), or the
+// interleaved basis itself when M = I (then z_k = v_k).
+template <typename KT, int MP, bool FROM_V>
 __global__ __launch_bounds__(BLOCK) void k_update_x(int64_t n, const KT *__restrict__ Z,
                                                     const double *__restrict__ y, const Ctl *ctl,
                                                     double *__restrict__ x) {
@@ -288,7 +484,10 @@ __global__ __launch_bounds__(BLOCK) void k_update_x(int64_t n, const KT *__restr
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * BLOCK) {
         double acc = 0.0;
-        for (int k = 0; k < ku; ++k) acc += (double)Z[(int64_t)k * n + i] * y[k];
+        if (FROM_V)
+            for (int k = 0; k < ku; ++k) acc += (double)Z[i * MP + k] * y[k];
+        else
+            for (int k = 0; k < ku; ++k) acc += (double)Z[(int64_t)k * n + i] * y[k];
         x[i] += acc;
     }
 }
@@ -296,23 +495,30 @@ __global__ __launch_bounds__(BLOCK) void k_update_x(int64_t n, const KT *__restr
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
+static int basis_pitch(int m) {
+    int mp = 32;
+    while (mp < m + 1) mp *= 2;
+    return mp;
+}
+
+// rows per block of the Gram-Schmidt kernels: one round of loads per lane
+// (RPP * 16 rows) unless n needs more than 1024 such blocks
+static int64_t cgs_rpb(int64_t n) {
+    int64_t rpb = RPP * 16;
+    while ((n + rpb - 1) / rpb > 1024) rpb *= 2;
+    return rpb;
+}
+
 void solve_ctx_free(SolveCtx *c) {
     if (!c) return;
-    void *ptrs[] = {c->V,  c->Z,  c->w,  c->r,  c->act[0], c->act[1], c->tau,     c->H,
-                    c->H0, c->cs, c->sn, c->g,  c->y,      c->h1,     c->h2,      c->hist,
-                    c->partial, c->counters, c->ctl};
+    void *ptrs[] = {c->V,  c->Z,  c->w,  c->r,  c->act[0], c->act[1], c->tau, c->H,
+                    c->H0, c->cs, c->sn, c->g,  c->y,      c->h1,     c->h2,  c->hist,
+                    c->partial, c->counters, c->ctl, c->vcur};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->ctl_host) (void)hipHostFree(c->ctl_host);
     if (c->ev) (void)hipEventDestroy(c->ev);
     *c = SolveCtx();
-}
-
-static int64_t cgs_rpb(int64_t n) {
-    int64_t nb = 512;
-    int64_t rpb = (n + nb - 1) / nb;
-    rpb = ((rpb + BLOCK - 1) / BLOCK) * BLOCK;
-    return rpb < BLOCK ? BLOCK : rpb;
 }
 
 gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
@@ -324,14 +530,17 @@ gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
     solve_ctx_free(c);
     c->sys = sys;
     c->m = m;
+    c->mp = basis_pitch(m);
     c->n = sys->n;
     c->prec = prec;
     c->kbytes = kb;
     c->maxiters_cap = std::max(maxiters, 128);
     c->act_d = act_d;
     const int64_t n = sys->n;
-    GNP_HIP(hipMalloc(&c->V, kb * (size_t)n * (m + 1)));
+    GNP_HIP(hipMalloc(&c->V, kb * (size_t)n * c->mp));
+    GNP_HIP(hipMemset(c->V, 0, kb * (size_t)n * c->mp));
     GNP_HIP(hipMalloc(&c->Z, kb * (size_t)n * m));
+    GNP_HIP(hipMalloc(&c->vcur, kb * (size_t)n));
     GNP_HIP(hipMalloc(&c->w, kb * (size_t)n));
     GNP_HIP(hipMalloc(&c->r, sizeof(double) * n));
     if (act_d > 0)
@@ -347,55 +556,80 @@ gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
     GNP_HIP(hipMalloc(&c->h2, sizeof(double) * (m + 1)));
     GNP_HIP(hipMalloc(&c->hist, sizeof(double) * (c->maxiters_cap + 1)));
     const int64_t nb_cgs = (n + cgs_rpb(n) - 1) / cgs_rpb(n);
-    c->npartial = std::max<int64_t>(nb_cgs * (m + 2), 4096);
+    c->npartial = std::max<int64_t>(nb_cgs * (c->mp + 1), 2048);
     GNP_HIP(hipMalloc(&c->partial, sizeof(double) * c->npartial));
-    GNP_HIP(hipMalloc(&c->counters, sizeof(unsigned) * 16));
-    GNP_HIP(hipMemset(c->counters, 0, sizeof(unsigned) * 16));
     GNP_HIP(hipMalloc(&c->ctl, sizeof(Ctl)));
     GNP_HIP(hipHostMalloc(&c->ctl_host, sizeof(Ctl), hipHostMallocDefault));
     GNP_HIP(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
     return GNP_OK;
 }
 
-template <typename KT>
-static gnp_status launch_cycle(SolveCtx *c, gnp_model *model, int nsteps, double *x,
-                               hipStream_t st) {
+template <typename KT, int MP>
+static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, double *x,
+                                  hipStream_t st) {
     gnp_system *s = c->sys;
     const int64_t n = s->n;
-    KT *V = (KT *)c->V, *Z = model ? (KT *)c->Z : (KT *)c->V, *w = (KT *)c->w;
+    KT *V = (KT *)c->V, *Z = (KT *)c->Z, *w = (KT *)c->w, *vcur = (KT *)c->vcur;
     const KT *val;
     if constexpr (sizeof(KT) == 8) val = (const KT *)s->val64;
     else val = (const KT *)s->val32;
     const int sg = stream_grid(n);
     const int64_t rpb = cgs_rpb(n);
     const int gcgs = (int)((n + rpb - 1) / rpb);
-    const int pstride = c->m + 2;
-    int *skip = &c->ctl->cycle_done;
-    hipLaunchKernelGGL((k_scale_norm<KT, double>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, V,
-                       c->partial, c->counters + 0, c->ctl, 1, c->tau);
+    const int pstride = MP + 1;
+    const int *skip = &c->ctl->cycle_done;
+    hipLaunchKernelGGL((k_normalize<KT, double, MP>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, V, 0,
+                       vcur, c->partial, c->ctl, 1);
+    hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau, c->ctl);
     for (int j = 0; j < nsteps; ++j) {
-        KT *vj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n;
+        KT *zj = model ? Z + (int64_t)j * n : vcur;
         if (model)
-            GNP_TRY(forward_launch(model, c->prec, vj, zj, 1, c->tau, c->act[0], c->act[1], skip,
+            GNP_TRY(forward_launch(model, c->prec, vcur, zj, 1, c->tau, c->act[0], c->act[1], skip,
                                    st));
         spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st);
-        hipLaunchKernelGGL((k_cgs<KT, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
-                           (const double *)nullptr, c->h1, c->partial, pstride, c->counters + 1,
-                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist);
-        hipLaunchKernelGGL((k_cgs<KT, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
-                           (const double *)c->h1, c->h2, c->partial, pstride, c->counters + 2,
-                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist);
-        hipLaunchKernelGGL((k_cgs<KT, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
-                           (const double *)c->h2, c->h1, c->partial, pstride, c->counters + 3,
-                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist);
-        hipLaunchKernelGGL((k_scale_norm<KT, KT>), dim3(sg), dim3(BLOCK), 0, st, n, w,
-                           V + (int64_t)(j + 1) * n, c->partial, c->counters + 4, c->ctl, 0,
-                           c->tau);
+        hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
+                           (const KT *)V, j, w, (const double *)nullptr, c->partial, pstride,
+                           (const Ctl *)c->ctl);
+        hipLaunchKernelGGL(k_fin_dots<0>, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, c->h1, c->ctl);
+        hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
+                           (const KT *)V, j, w, (const double *)c->h1, c->partial, pstride,
+                           (const Ctl *)c->ctl);
+        hipLaunchKernelGGL(k_fin_dots<1>, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, c->h2, c->ctl);
+        hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
+                           (const KT *)V, j, w, (const double *)c->h2, c->partial, pstride,
+                           (const Ctl *)c->ctl);
+        hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, (const double *)c->h1,
+                           (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
+                           c->hist);
+        hipLaunchKernelGGL((k_normalize<KT, KT, MP>), dim3(sg), dim3(BLOCK), 0, st, n,
+                           (const KT *)w, V, j + 1, vcur, c->partial, c->ctl, 0);
+        hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
+                           c->ctl);
     }
-    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(WAVE), 0, st, c->ctl, c->H, c->g, c->y);
-    hipLaunchKernelGGL((k_update_x<KT>), dim3(sg), dim3(BLOCK), 0, st, n, Z, c->y, c->ctl, x);
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(BLOCK), 0, st, c->ctl, c->H, c->g, c->y);
+    if (model)
+        hipLaunchKernelGGL((k_update_x<KT, MP, false>), dim3(sg), dim3(BLOCK), 0, st, n,
+                           (const KT *)Z, c->y, c->ctl, x);
+    else
+        hipLaunchKernelGGL((k_update_x<KT, MP, true>), dim3(sg), dim3(BLOCK), 0, st, n,
+                           (const KT *)V, c->y, c->ctl, x);
     GNP_HIP(hipGetLastError());
     return GNP_OK;
+}
+
+template <typename KT>
+static gnp_status launch_cycle(SolveCtx *c, gnp_model *model, int nsteps, double *x,
+                               hipStream_t st) {
+    switch (c->mp) {
+        case 32: return launch_cycle_mp<KT, 32>(c, model, nsteps, x, st);
+        case 64: return launch_cycle_mp<KT, 64>(c, model, nsteps, x, st);
+        case 128: return launch_cycle_mp<KT, 128>(c, model, nsteps, x, st);
+        case 256: return launch_cycle_mp<KT, 256>(c, model, nsteps, x, st);
+        default: return fail(GNP_EINVAL, "unsupported basis pitch");
+    }
 }
 
 static void launch_residual(SolveCtx *c, const double *b, const double *x, int initial,
@@ -403,15 +637,15 @@ static void launch_residual(SolveCtx *c, const double *b, const double *x, int i
     gnp_system *s = c->sys;
     const int64_t n = s->n;
     const double avg = (double)s->nnz / (double)n;
-    const int grid = grid_for(n, BLOCK / 8, 2048);
+    const int grid = grid_for(n, BLOCK / 8, 1024);
     if (avg <= 8.0)
         hipLaunchKernelGGL(k_residual<8>, dim3(grid), dim3(BLOCK), 0, st, n, s->rp, s->ci,
-                           s->val64, x, b, c->r, c->partial, c->counters + 5, c->ctl, c->g,
-                           c->hist, initial);
+                           s->val64, x, b, c->r, c->partial);
     else
         hipLaunchKernelGGL(k_residual<16>, dim3(grid), dim3(BLOCK), 0, st, n, s->rp, s->ci,
-                           s->val64, x, b, c->r, c->partial, c->counters + 5, c->ctl, c->g,
-                           c->hist, initial);
+                           s->val64, x, b, c->r, c->partial);
+    hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(BLOCK), 0, st, grid,
+                       (const double *)c->partial, c->ctl, c->g, c->hist, initial);
 }
 
 gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, int m,
@@ -425,8 +659,10 @@ gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, 
     init.maxiters = maxiters;
     *c->ctl_host = init;
     GNP_HIP(hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_bnorm, dim3(stream_grid(n)), dim3(BLOCK), 0, st, n, b, rtol, c->partial,
-                       c->counters + 6, c->ctl);
+    const int sg = stream_grid(n);
+    hipLaunchKernelGGL(k_sumsq, dim3(sg), dim3(BLOCK), 0, st, n, b, c->partial);
+    hipLaunchKernelGGL(k_fin_bnorm, dim3(1), dim3(BLOCK), 0, st, sg, (const double *)c->partial,
+                       rtol, c->ctl);
     launch_residual(c, b, x, 1, st);
     GNP_HIP(hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     GNP_HIP(hipStreamSynchronize(st));
@@ -477,7 +713,7 @@ extern "C" gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const doub
                                    gnp_precision prec, double *hist, gnp_solve_info *info,
                                    void *hip_stream) {
     if (!sys || !b_dev || !x_dev) return fail(GNP_EINVAL, "null argument");
-    if (m < 1 || m > 256) return fail(GNP_EINVAL, "m must be in [1, 256]");
+    if (m < 1 || m > 255) return fail(GNP_EINVAL, "m must be in [1, 255]");
     if (!(rtol > 0.0)) return fail(GNP_EINVAL, "rtol must be > 0");
     if (maxiters < 1) return fail(GNP_EINVAL, "maxiters must be >= 1");
     if (!valid_precision(prec)) return fail(GNP_EINVAL, "bad precision");

@@ -25,12 +25,14 @@ struct Ctl {
 struct SolveCtx {
     gnp_system *sys = nullptr;
     int m = 0;
+    int mp = 32;            // row pitch of the interleaved basis
     int maxiters_cap = 0;
     gnp_precision prec = GNP_F32;
     int64_t n = 0;
     size_t kbytes = 4;      // bytes per Krylov element
-    void *V = nullptr;      // (m+1) x n
-    void *Z = nullptr;      // m x n
+    void *V = nullptr;      // n x mp, row-interleaved basis (entries k <= m used)
+    void *Z = nullptr;      // m x n, column-major network outputs
+    void *vcur = nullptr;   // n, the current basis vector (network input)
     void *w = nullptr;      // n
     double *r = nullptr;    // n, float64 residual
     void *act[2] = {nullptr, nullptr};

@@ -382,3 +382,25 @@ gnp_status gnp_spmv(const gnp_system *sys, const void *x_dev, void *y_dev, gnp_p
 }
 
 }  // extern "C"
+
+extern "C" gnp_status gnp_time_spmv(const gnp_system *sys, const void *x_dev, void *y_dev,
+                                    gnp_precision prec, int reps, double *ms_per_launch,
+                                    void *hip_stream) {
+    if (!sys || !x_dev || !y_dev || !ms_per_launch || reps < 1)
+        return fail(GNP_EINVAL, "bad argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    GNP_HIP(hipEventCreate(&e0));
+    GNP_HIP(hipEventCreate(&e1));
+    GNP_TRY(gnp_spmv(sys, x_dev, y_dev, prec, hip_stream));
+    GNP_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) GNP_TRY(gnp_spmv(sys, x_dev, y_dev, prec, hip_stream));
+    GNP_HIP(hipEventRecord(e1, st));
+    GNP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GNP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = (double)ms / reps;
+    return GNP_OK;
+}

@@ -173,7 +173,7 @@ def _iters_close(it, it_ref):
     return abs(it - it_ref) <= max(1, int(np.ceil(0.1 * it_ref)))
 
 
-@pytest.mark.parametrize("m", [10, 30])
+@pytest.mark.parametrize("m", [1, 10, 30, 40, 70])
 def test_fgmres_identity_f64_matches_oracle(api, m):
     A = I.convdiff3d(12)
     S = api.System(A)
@@ -185,7 +185,7 @@ def test_fgmres_identity_f64_matches_oracle(api, m):
     assert info["converged"] == 1 and r["info"]["converged"] == 1
     assert info["iters"] == r["info"]["iters"]
     assert info["restarts"] == r["info"]["restarts"]
-    np.testing.assert_allclose(hist, r["hist"], rtol=1e-9)
+    np.testing.assert_allclose(hist, r["hist"], rtol=1e-9, atol=1e-15)
     xs = x.cpu().numpy()
     assert np.linalg.norm(xs - r["x"]) <= 1e-9 * np.linalg.norm(r["x"])
     true = np.linalg.norm(b - ref.A.to_scipy() @ xs) / np.linalg.norm(b)
@@ -239,7 +239,7 @@ def test_fgmres_edge_cases(api):
     x, info, hist = api.fgmres_solve(S, b, None, m=5, rtol=1e-8, maxiters=1, prec="f32")
     assert info["iters"] == 1 and info["converged"] == 0
     from paper_2406_00809_amd._lib import GNPError
-    for kw in (dict(m=0), dict(rtol=0.0), dict(maxiters=0), dict(m=300)):
+    for kw in (dict(m=0), dict(rtol=0.0), dict(maxiters=0), dict(m=256)):
         args = dict(m=5, rtol=1e-8, maxiters=10)
         args.update(kw)
         with pytest.raises(GNPError):
