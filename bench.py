@@ -70,6 +70,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--allow-nonconverged", action="store_true",
                     help="report instead of failing when a timed solve does not converge")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="profiling mode: launch the layer kernel and the SpMV in the bench's "
+                         "configuration plus a 256 MiB device copy (counter calibration), "
+                         "no training or solves")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the float32-network comparison solves")
     args = ap.parse_args()
@@ -92,6 +96,20 @@ def main():
     th0 = I.init_params(L, d, h, 12)
     M = api.Model(S, L, d, h, th0)
     log(f"system n={S.n} nnz={S.nnz} gamma={S.gamma_input:.6f}")
+    if args.kernels_only:
+        v = torch.randn(S.n, dtype=torch.float32, device=dev)
+        M.apply(v, prec=args.prec)
+        ms = M.time_layer(nrhs=1, prec=args.prec, reps=20)
+        yv = torch.empty_like(v)
+        sms = S.time_spmv(v, yv, prec="f32", reps=20)
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"layer_us": 1e3 * ms, "spmv_us": 1e3 * sms,
+                          "copy_bytes_each_way": 256 << 20}), flush=True)
+        return
 
     # ---- setup (untimed): train the preconditioner on the device
     torch.cuda.synchronize()

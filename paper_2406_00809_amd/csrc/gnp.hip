@@ -192,11 +192,13 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
     for (int l = 0; l < m->L; ++l) {
         const G *X = bufs[l % 2];
         if (l < m->L - 1) {
-            hipLaunchKernelGGL((k_layer<G, D, H, false, ZT>), dim3(grid), dim3(BLOCK), 0, st, rows,
+            hipLaunchKernelGGL((k_layer<G, D, H, false, ZT>),
+                               dim3(layer_grid<G, D, H, false, ZT>(rows)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, bufs[(l + 1) % 2], wcat(l), w3, vec,
                                po.c3, po.W4, po.c4, tau, z, skip);
         } else {
-            hipLaunchKernelGGL((k_layer<G, D, H, true, ZT>), dim3(grid), dim3(BLOCK), 0, st, rows,
+            hipLaunchKernelGGL((k_layer<G, D, H, true, ZT>),
+                               dim3(layer_grid<G, D, H, true, ZT>(rows)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, (G *)nullptr, wcat(l), w3, vec, po.c3,
                                po.W4, po.c4, tau, z, skip);
         }
@@ -224,6 +226,8 @@ static void forward_dispatch(gnp_model *m, gnp_precision prec, const void *v, vo
 gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                           const double *tau, void *act0, void *act1, const int *skip,
                           hipStream_t st) {
+    if (m->sys->n * (int64_t)nrhs * m->d >= (int64_t)1 << 31)
+        return fail(GNP_EINVAL, "n * nrhs * d must stay below 2^31 (32-bit gather offsets)");
     if (m->d == 16)
         forward_dispatch<16, 32>(m, prec, v, z, nrhs, tau, act0, act1, skip, st);
     else
@@ -238,7 +242,7 @@ template <typename G, int D, int H>
 static void layer_once(gnp_model *m, int nrhs, int l, hipStream_t st) {
     gnp_system *s = m->sys;
     const int64_t rows = s->n * (int64_t)nrhs;
-    const int grid = grid_for(rows, 64);
+    const int grid = layer_grid<G, D, H, false, float>(rows);
     const void *wc;
     const typename Act<G>::vt *ahat;
     const typename Act<G>::acc *vec;

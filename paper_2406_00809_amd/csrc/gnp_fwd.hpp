@@ -1,9 +1,9 @@
 // Forward kernels of the graph neural preconditioner (Sec. 2.3).
 //
 // Rows of the activation matrices are (node, right-hand side) pairs,
-// r = i * nrhs + k, node-major, with d features per row.  Every kernel runs
-// 256-thread blocks of four wavefronts; each wavefront owns one tile of 16
-// consecutive rows, so a block covers 64 rows.
+// r = i * nrhs + k, node-major, with d features per row.  Kernels run
+// 256-thread blocks of four wavefronts; a wavefront works on tiles of 16
+// consecutive rows.
 //
 // Arithmetic per activation storage type G:
 //   double   : FP64 VALU (reference-precision instantiation)
@@ -14,6 +14,10 @@
 //   A (16 x K):  row = l % 16, k-slot = l / 16 (f32: 1 value; bf16: 8 values)
 //   B (K x 16):  col = l % 16, same k-slot as A
 //   D (16 x 16): col = l % 16, rows 4 * (l / 16) + j, j = 0..3
+// The products are formed transposed, Y^T = W^T X^T: the packed weight
+// fragments are the A operand and the activation tile the B operand, so a
+// lane's four results are four consecutive features (4 (l/16) + j) of one row
+// (l % 16) and leave as a single 8- or 16-byte store.
 #pragma once
 #include "model.hpp"
 
@@ -65,6 +69,20 @@ __device__ __forceinline__ void store_feats(G *p, const typename Act<G>::acc (&i
     *reinterpret_cast<Chunk<BYTES> *>(p) = c;
 }
 
+// Store four consecutive features held by one lane.
+template <typename G> __device__ __forceinline__ void store4(G *p, float a, float b, float c, float d);
+template <>
+__device__ __forceinline__ void store4<float>(float *p, float a, float b, float c, float d) {
+    *reinterpret_cast<float4 *>(p) = make_float4(a, b, c, d);
+}
+template <>
+__device__ __forceinline__ void store4<uint16_t>(uint16_t *p, float a, float b, float c, float d) {
+    uint2 u;
+    u.x = (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+    u.y = (uint32_t)f2bf(c) | ((uint32_t)f2bf(d) << 16);
+    *reinterpret_cast<uint2 *>(p) = u;
+}
+
 template <typename T> __device__ __forceinline__ T relu(T x) { return x > (T)0 ? x : (T)0; }
 
 // Every LDS region of these kernels belongs to one wavefront, and a
@@ -88,7 +106,8 @@ template <typename G> constexpr int lds_pad() {
 
 // ---------------------------------------------------------------------------
 // Encoder: E = ReLU(u W1 + c1) W2 + c2 with u = (sqrt(n)/tau) v  (Eq. (6)).
-// The hidden activations form the MFMA A operand directly in registers.
+// The hidden activations of row l % 16 are built in registers as the B
+// operand of E^T = W2^T hid^T.
 // ---------------------------------------------------------------------------
 template <typename G, typename IN, int D, int H>
 __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN *__restrict__ v,
@@ -120,7 +139,6 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
         for (int e = 0; e < D / 4; ++e) out[e] += c2[q * (D / 4) + e];
         store_feats<G, D / 4>(E + r * D + q * (D / 4), out);
     } else {
-        __shared__ __attribute__((aligned(16))) G Es[BLOCK / WAVE][16][D + 8];
         const int64_t ra = r0 + lane % 16;
         const float u = ra < rows ? (float)(tau[3 * (ra % B) + 1] * (double)v[ra]) : 0.f;
         f32x4 o[D / 16];
@@ -135,7 +153,7 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
 #pragma unroll
                 for (int nt = 0; nt < D / 16; ++nt)
                     o[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        a, pk[(ks * (D / 16) + nt) * 64 + lane], o[nt], 0, 0, 0);
+                        pk[(ks * (D / 16) + nt) * 64 + lane], a, o[nt], 0, 0, 0);
             }
         } else {
             const uint16_t *pk = (const uint16_t *)w2;
@@ -147,30 +165,21 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
                     const int k = kb * 32 + 8 * (lane / 16) + i;
                     av[i] = f2bf(fmaxf(u * W1[k] + c1[k], 0.f));
                 }
-                const bf16x8 af = __builtin_bit_cast(bf16x8, av);
+                const bf16x8 hf = __builtin_bit_cast(bf16x8, av);
 #pragma unroll
                 for (int nt = 0; nt < D / 16; ++nt)
                     o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        af, load_bf16x8(pk + ((int64_t)(kb * (D / 16) + nt) * 64 + lane) * 8),
+                        load_bf16x8(pk + ((int64_t)(kb * (D / 16) + nt) * 64 + lane) * 8), hf,
                         o[nt], 0, 0, 0);
             }
         }
-        // stage the 16 x D output tile in LDS, then 16-byte coalesced stores
+        if (ra < rows) {
 #pragma unroll
-        for (int nt = 0; nt < D / 16; ++nt) {
-            const int col = nt * 16 + lane % 16;
-            const float cb = c2[col];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) Es[wv][4 * (lane / 16) + j][col] = Act<G>::put(o[nt][j] + cb);
-        }
-        wave_lds_sync();
-        const int rl = lane / 4, q = lane % 4;
-        const int64_t r = r0 + rl;
-        if (r < rows) {
-            typename Act<G>::acc ov[D / 4];
-#pragma unroll
-            for (int e = 0; e < D / 4; ++e) ov[e] = Act<G>::get(Es[wv][rl][q * (D / 4) + e]);
-            store_feats<G, D / 4>(E + r * D + q * (D / 4), ov);
+            for (int nt = 0; nt < D / 16; ++nt) {
+                const int f = nt * 16 + 4 * (lane / 16);
+                store4<G>(E + ra * D + f, o[nt][0] + c2[f], o[nt][1] + c2[f + 1],
+                          o[nt][2] + c2[f + 2], o[nt][3] + c2[f + 3]);
+            }
         }
     }
 }
@@ -180,6 +189,14 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
 // row, d/4 features per lane) -> LDS tile [X | T] -> [X | T] [U; W] on MFMA
 // -> ReLU -> store.  With DEC the output tile stays in LDS and feeds the
 // decoder  o = ReLU(Y W3 + c3) W4 + c4,  z = (tau/sqrt(n)) o  (Eq. (6)).
+//
+// Persistent, software-pipelined walk over 16-row tiles (stride = number of
+// wavefronts in the grid).  Tile t touches nodes ifirst..ilast whose nonzeros
+// are contiguous in CSR; that slice (colind, values, rowptr offsets) is
+// staged in the wavefront's LDS.  The rowptr slice of the next tile is
+// requested before the gathers of the current one, and its colind / value
+// slice (into registers) before the current tile's MFMA and stores.
+// Gather offsets are 32-bit (the launchers check rows * d < 2^31).
 // ---------------------------------------------------------------------------
 template <typename G, int D, int H, bool DEC, typename ZT>
 __global__ __launch_bounds__(BLOCK) void k_layer(
@@ -191,234 +208,293 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
     if (skip && *skip) return;
     using acc_t = typename Act<G>::acc;
     using mt = typename Act<G>::mt;
-    constexpr int LD = 2 * D + lds_pad<G>();
-    __shared__ __attribute__((aligned(16))) mt As[BLOCK / WAVE][16][LD];
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    const int64_t r0 = ((int64_t)blockIdx.x * (BLOCK / WAVE) + wv) * 16;
-
-    // ---- stage the tile's slice of the CSR arrays (rows r0 .. r0+15 touch
-    // nodes ifirst .. ilast, whose nonzeros are contiguous) in LDS
     using vt_t = typename Act<G>::vt;
-    constexpr int CAP = 256;
+    constexpr int LD = 2 * D + lds_pad<G>();
+    constexpr int CAP = 256, NC = CAP / WAVE;
+    __shared__ __attribute__((aligned(16))) mt As[BLOCK / WAVE][16][LD];
     __shared__ int32_t sRp[BLOCK / WAVE][17];
     __shared__ int32_t sCi[BLOCK / WAVE][CAP];
     __shared__ vt_t sVa[BLOCK / WAVE][CAP];
-    const bool live = r0 < rows;
-    const int64_t rlast = (r0 + 15 < rows) ? r0 + 15 : rows - 1;
-    const int64_t ifirst = live ? ((B == 1) ? r0 : r0 / B) : 0;
-    const int64_t ilast = live ? ((B == 1) ? rlast : rlast / B) : 0;
-    const int32_t kbeg = live ? rp[ifirst] : 0;
-    const int32_t cnt = live ? rp[ilast + 1] - kbeg : 0;
-    const bool staged = cnt <= CAP;
-    if (live && lane <= (int)(ilast - ifirst)) sRp[wv][lane] = rp[ifirst + lane] - kbeg;
-    if (live && lane == 0) sRp[wv][ilast - ifirst + 1] = cnt;
-    if (live && staged) {
-        for (int t2 = lane; t2 < cnt; t2 += WAVE) {
-            sCi[wv][t2] = ci[kbeg + t2];
-            sVa[wv][t2] = ahat[kbeg + t2];
-        }
-    }
-    wave_lds_sync();
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int64_t ntiles = (rows + 15) / 16;
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
 
-    // ---- phase 1: gather T = A-hat X and the row's own X into LDS
-    {
-        const int rl = lane / 4, q = lane % 4;
-        const int64_t r = r0 + rl;
-        acc_t t[D / 4], s[D / 4];
+    auto node_range = [&](int64_t t, int64_t &ifirst, int &nn) {
+        const int64_t r0 = t * 16;
+        const int64_t rlast = (r0 + 15 < rows) ? r0 + 15 : rows - 1;
+        ifirst = (B == 1) ? r0 : r0 / B;
+        nn = (int)(((B == 1) ? rlast : rlast / B) - ifirst) + 1;
+    };
+    auto fetch_rp = [&](int64_t t, int32_t &rpv) {
+        int64_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        rpv = lane <= nn ? rp[ifirst + lane] : 0;
+    };
+    auto fetch_csr = [&](int64_t t, int32_t rpv, int32_t &kbeg, int32_t &cnt, int32_t (&cv)[NC],
+                         vt_t (&av)[NC]) {
+        int64_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        kbeg = __shfl(rpv, 0, WAVE);
+        cnt = __shfl(rpv, nn, WAVE) - kbeg;
+        if (cnt > 0 && cnt <= CAP) {  // cnt = 0: empty rows, nothing to load
 #pragma unroll
-        for (int e = 0; e < D / 4; ++e) t[e] = s[e] = (acc_t)0;
-        if (r < rows) {
-            const int64_t i = (B == 1) ? r : r / B;
-            const int b = (int)(r - i * B);
-            const int li = (int)(i - ifirst);
-            const int32_t ks = sRp[wv][li], ke = sRp[wv][li + 1];
-            load_feats<G, D / 4>(X + r * D + q * (D / 4), s);
-            if (staged) {
-                // neighbours in batches of NB: all gathers issued before the FMAs;
-                // short rows re-load a valid neighbour with weight 0
-                constexpr int NB = sizeof(G) == 2 ? 8 : 4;
-                constexpr int CB = (D / 4) * (int)sizeof(G);
-                for (int32_t k0 = ks; k0 < ke; k0 += NB) {
-                    Chunk<CB> raw[NB];  // packed until the FMAs (register economy)
-                    acc_t av[NB];
+            for (int u = 0; u < NC; ++u) {
+                const int idx = lane + WAVE * u;
+                const int idc = idx < cnt ? idx : 0;
+                cv[u] = ci[kbeg + idc];
+                av[u] = ahat[kbeg + idc];
+            }
+        }
+    };
+
+    int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
+    int32_t rpv = 0, kbeg = 0, cnt = 0;
+    int32_t cv[NC];
+    vt_t av[NC];
+    if (t < ntiles) {
+        fetch_rp(t, rpv);
+        fetch_csr(t, rpv, kbeg, cnt, cv, av);
+    }
+    for (; t < ntiles; t += nw) {
+        const int64_t r0 = t * 16;
+        int64_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        const bool staged = cnt <= CAP;
+        // ---- commit this tile's CSR slice to LDS
+        if (lane <= nn) sRp[wv][lane] = rpv - kbeg;
+        if (staged) {
 #pragma unroll
-                    for (int u = 0; u < NB; ++u) {
-                        const bool ok = k0 + u < ke;
-                        const int32_t kk = ok ? k0 + u : ks;
-                        const int64_t c = sCi[wv][kk];
-                        av[u] = ok ? (acc_t)sVa[wv][kk] : (acc_t)0;
-                        raw[u] = *reinterpret_cast<const Chunk<CB> *>(X + (c * B + b) * D +
-                                                                      q * (D / 4));
-                    }
-#pragma unroll
-                    for (int u = 0; u < NB; ++u) {
-                        const G *e8 = reinterpret_cast<const G *>(&raw[u]);
-#pragma unroll
-                        for (int e = 0; e < D / 4; ++e) t[e] += av[u] * Act<G>::get(e8[e]);
-                    }
-                }
-            } else {
-                for (int32_t k = kbeg + ks; k < kbeg + ke; ++k) {
-                    const int64_t c = ci[k];
-                    const acc_t a = (acc_t)ahat[k];
-                    acc_t xv[D / 4];
-                    load_feats<G, D / 4>(X + (c * B + b) * D + q * (D / 4), xv);
-#pragma unroll
-                    for (int e = 0; e < D / 4; ++e) t[e] += a * xv[e];
+            for (int u = 0; u < NC; ++u) {
+                const int idx = lane + WAVE * u;
+                if (idx < cnt) {
+                    sCi[wv][idx] = cv[u];
+                    sVa[wv][idx] = av[u];
                 }
             }
         }
-#pragma unroll
-        for (int e = 0; e < D / 4; ++e) {
-            As[wv][rl][q * (D / 4) + e] = Act<G>::put(s[e]);
-            As[wv][rl][D + q * (D / 4) + e] = Act<G>::put(t[e]);
-        }
-    }
-    wave_lds_sync();
+        const int64_t tn = t + nw;
+        int32_t rpn = 0;
+        if (tn < ntiles) fetch_rp(tn, rpn);
+        wave_lds_sync();
 
-    if constexpr (sizeof(G) == 8) {
-        // ---- FP64 VALU path
-        const double *Wc = (const double *)wcat;
-        const int rl = lane / 4, q = lane % 4;
-        const int64_t r = r0 + rl;
-        double y[D / 4];
-#pragma unroll
-        for (int e = 0; e < D / 4; ++e) {
-            const int col = q * (D / 4) + e;
-            double sacc = 0.0;
-            for (int k = 0; k < 2 * D; ++k) sacc += As[wv][rl][k] * Wc[(int64_t)k * D + col];
-            y[e] = relu(sacc);
-        }
-        if constexpr (!DEC) {
-            if (r < rows) store_feats<G, D / 4>(Y + r * D + q * (D / 4), y);
-        } else {
-            wave_lds_sync();
-#pragma unroll
-            for (int e = 0; e < D / 4; ++e) As[wv][rl][q * (D / 4) + e] = y[e];
-            wave_lds_sync();
-            const double *W3 = (const double *)w3;
-            const double *c3 = vec + oc3, *W4 = vec + oW4;
-            double part = 0.0;
-            for (int kk = 0; kk < H / 4; ++kk) {
-                const int k = q * (H / 4) + kk;
-                double hs = c3[k];
-                for (int f = 0; f < D; ++f) hs += As[wv][rl][f] * W3[(int64_t)f * H + k];
-                part += relu(hs) * W4[k];
-            }
-            part += __shfl_xor(part, 1, 4);
-            part += __shfl_xor(part, 2, 4);
-            if (q == 0 && r < rows) {
-                const int b = (int)(r % B);
-                z[r] = (ZT)(tau[3 * b + 2] * (part + vec[oc4]));
-            }
-        }
-    } else {
-        // ---- MFMA path: [X | T] (16 x 2D) times [U; W] (2D x D)
-        f32x4 o[D / 16];
-#pragma unroll
-        for (int nt = 0; nt < D / 16; ++nt) o[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if constexpr (sizeof(G) == 4) {
-            const float *pk = (const float *)wcat;
-#pragma unroll 8
-            for (int ks = 0; ks < 2 * D / 4; ++ks) {
-                const float a = As[wv][lane % 16][ks * 4 + lane / 16];
-#pragma unroll
-                for (int nt = 0; nt < D / 16; ++nt)
-                    o[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        a, pk[(ks * (D / 16) + nt) * 64 + lane], o[nt], 0, 0, 0);
-            }
-        } else {
-            const uint16_t *pk = (const uint16_t *)wcat;
-#pragma unroll
-            for (int kb = 0; kb < 2 * D / 32; ++kb) {
-                const bf16x8 af = load_bf16x8(&As[wv][lane % 16][kb * 32 + 8 * (lane / 16)]);
-#pragma unroll
-                for (int nt = 0; nt < D / 16; ++nt)
-                    o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        af, load_bf16x8(pk + ((int64_t)(kb * (D / 16) + nt) * 64 + lane) * 8),
-                        o[nt], 0, 0, 0);
-            }
-        }
-        if constexpr (!DEC) {
-            wave_lds_sync();  // every lane has read its A fragments
-#pragma unroll
-            for (int nt = 0; nt < D / 16; ++nt) {
-                const int col = nt * 16 + lane % 16;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    As[wv][4 * (lane / 16) + j][col] = Act<G>::put(relu(o[nt][j]));
-            }
-            wave_lds_sync();
+        // ---- phase 1: gather T = A-hat X and the row's own X into the LDS tile
+        {
             const int rl = lane / 4, q = lane % 4;
             const int64_t r = r0 + rl;
-            if (r < rows) {
-                acc_t ov[D / 4];
+            acc_t ta[D / 4], sv[D / 4];
 #pragma unroll
-                for (int e = 0; e < D / 4; ++e) ov[e] = Act<G>::get(As[wv][rl][q * (D / 4) + e]);
-                store_feats<G, D / 4>(Y + r * D + q * (D / 4), ov);
+            for (int e = 0; e < D / 4; ++e) ta[e] = sv[e] = (acc_t)0;
+            if (r < rows) {
+                const int64_t i = (B == 1) ? r : r / B;
+                const int b = (int)(r - i * B);
+                const int li = (int)(i - ifirst);
+                const int32_t ks = sRp[wv][li], ke = sRp[wv][li + 1];
+                load_feats<G, D / 4>(X + r * D + q * (D / 4), sv);
+                if (staged) {
+                    // neighbours in batches of NB, kept packed until the FMAs;
+                    // short rows re-load a valid neighbour with weight 0
+                    constexpr int NB = sizeof(G) == 2 ? 8 : 4;
+                    constexpr int CB = (D / 4) * (int)sizeof(G);
+                    for (int32_t k0 = ks; k0 < ke; k0 += NB) {
+                        Chunk<CB> raw[NB];
+                        acc_t wgt[NB];
+#pragma unroll
+                        for (int u = 0; u < NB; ++u) {
+                            const bool ok = k0 + u < ke;
+                            const int32_t kk = ok ? k0 + u : ks;
+                            const uint32_t c = (uint32_t)sCi[wv][kk];
+                            wgt[u] = ok ? (acc_t)sVa[wv][kk] : (acc_t)0;
+                            const uint32_t off = (c * (uint32_t)B + (uint32_t)b) * (uint32_t)D +
+                                                 (uint32_t)(q * (D / 4));
+                            raw[u] = *reinterpret_cast<const Chunk<CB> *>(X + off);
+                        }
+#pragma unroll
+                        for (int u = 0; u < NB; ++u) {
+                            const G *e8 = reinterpret_cast<const G *>(&raw[u]);
+#pragma unroll
+                            for (int e = 0; e < D / 4; ++e) ta[e] += wgt[u] * Act<G>::get(e8[e]);
+                        }
+                    }
+                } else {
+                    for (int32_t k = kbeg + ks; k < kbeg + ke; ++k) {
+                        const uint32_t c = (uint32_t)ci[k];
+                        const acc_t a = (acc_t)ahat[k];
+                        acc_t xv[D / 4];
+                        load_feats<G, D / 4>(
+                            X + (c * (uint32_t)B + (uint32_t)b) * (uint32_t)D + q * (D / 4), xv);
+#pragma unroll
+                        for (int e = 0; e < D / 4; ++e) ta[e] += a * xv[e];
+                    }
+                }
+            }
+            store_feats<mt, D / 4>(&As[wv][rl][q * (D / 4)], sv);
+            store_feats<mt, D / 4>(&As[wv][rl][D + q * (D / 4)], ta);
+        }
+        // ---- prefetch the next tile's colind / value slice into registers
+        int32_t kbeg_n = 0, cnt_n = 0;
+        int32_t cv_n[NC];
+        vt_t av_n[NC];
+        if (tn < ntiles) fetch_csr(tn, rpn, kbeg_n, cnt_n, cv_n, av_n);
+        wave_lds_sync();
+
+        if constexpr (sizeof(G) == 8) {
+            // ---- FP64 VALU path
+            const double *Wc = (const double *)wcat;
+            const int rl = lane / 4, q = lane % 4;
+            const int64_t r = r0 + rl;
+            double y[D / 4];
+#pragma unroll
+            for (int e = 0; e < D / 4; ++e) {
+                const int col = q * (D / 4) + e;
+                double sacc = 0.0;
+                for (int k = 0; k < 2 * D; ++k) sacc += As[wv][rl][k] * Wc[(int64_t)k * D + col];
+                y[e] = relu(sacc);
+            }
+            if constexpr (!DEC) {
+                if (r < rows) store_feats<G, D / 4>(Y + r * D + q * (D / 4), y);
+            } else {
+                wave_lds_sync();
+#pragma unroll
+                for (int e = 0; e < D / 4; ++e) As[wv][rl][q * (D / 4) + e] = y[e];
+                wave_lds_sync();
+                const double *W3 = (const double *)w3;
+                const double *c3 = vec + oc3, *W4 = vec + oW4;
+                double part = 0.0;
+                for (int kk = 0; kk < H / 4; ++kk) {
+                    const int k = q * (H / 4) + kk;
+                    double hs = c3[k];
+                    for (int f = 0; f < D; ++f) hs += As[wv][rl][f] * W3[(int64_t)f * H + k];
+                    part += relu(hs) * W4[k];
+                }
+                part += __shfl_xor(part, 1, 4);
+                part += __shfl_xor(part, 2, 4);
+                if (q == 0 && r < rows) {
+                    const int b = (int)(r % B);
+                    z[r] = (ZT)(tau[3 * b + 2] * (part + vec[oc4]));
+                }
             }
         } else {
-            wave_lds_sync();
-            constexpr int KP = (sizeof(G) == 2) ? ((D + 31) / 32) * 32 : D;
+            // ---- MFMA path: Y^T = [U; W]^T [X | T]^T, lane gets row l % 16
+            f32x4 o[D / 16];
 #pragma unroll
-            for (int nt = 0; nt < D / 16; ++nt) {
-                const int col = nt * 16 + lane % 16;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    As[wv][4 * (lane / 16) + j][col] = Act<G>::put(relu(o[nt][j]));
-                    if constexpr (KP > D) As[wv][4 * (lane / 16) + j][D + col] = Act<G>::put(0.f);
-                }
-            }
-            wave_lds_sync();
-            f32x4 hacc[H / 16];
-#pragma unroll
-            for (int nt = 0; nt < H / 16; ++nt) hacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < D / 16; ++nt) o[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
             if constexpr (sizeof(G) == 4) {
-                const float *pk = (const float *)w3;
-#pragma unroll 4
-                for (int ks = 0; ks < D / 4; ++ks) {
+                const float *pk = (const float *)wcat;
+#pragma unroll 8
+                for (int ks = 0; ks < 2 * D / 4; ++ks) {
                     const float a = As[wv][lane % 16][ks * 4 + lane / 16];
 #pragma unroll
-                    for (int nt = 0; nt < H / 16; ++nt)
-                        hacc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            a, pk[(ks * (H / 16) + nt) * 64 + lane], hacc[nt], 0, 0, 0);
+                    for (int nt = 0; nt < D / 16; ++nt)
+                        o[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            pk[(ks * (D / 16) + nt) * 64 + lane], a, o[nt], 0, 0, 0);
                 }
             } else {
-                const uint16_t *pk = (const uint16_t *)w3;
+                const uint16_t *pk = (const uint16_t *)wcat;
 #pragma unroll
-                for (int kb = 0; kb < KP / 32; ++kb) {
-                    const bf16x8 af = load_bf16x8(&As[wv][lane % 16][kb * 32 + 8 * (lane / 16)]);
+                for (int kb = 0; kb < 2 * D / 32; ++kb) {
+                    const bf16x8 xf = load_bf16x8(&As[wv][lane % 16][kb * 32 + 8 * (lane / 16)]);
 #pragma unroll
-                    for (int nt = 0; nt < H / 16; ++nt)
-                        hacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            af, load_bf16x8(pk + ((int64_t)(kb * (H / 16) + nt) * 64 + lane) * 8),
-                            hacc[nt], 0, 0, 0);
+                    for (int nt = 0; nt < D / 16; ++nt)
+                        o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            load_bf16x8(pk + ((int64_t)(kb * (D / 16) + nt) * 64 + lane) * 8), xf,
+                            o[nt], 0, 0, 0);
                 }
             }
-            const float *c3 = vec + oc3, *W4 = vec + oW4;
-            float part[4] = {0.f, 0.f, 0.f, 0.f};
+            const int64_t r = r0 + lane % 16;
+            if constexpr (!DEC) {
+                if (r < rows) {
 #pragma unroll
-            for (int nt = 0; nt < H / 16; ++nt) {
-                const int col = nt * 16 + lane % 16;
-                const float cb = c3[col], w4 = W4[col];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) part[j] += fmaxf(hacc[nt][j] + cb, 0.f) * w4;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                for (int off = 8; off > 0; off >>= 1) part[j] += __shfl_xor(part[j], off, 16);
-            }
-            if (lane % 16 == 0) {
-                const float c4 = vec[oc4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int64_t r = r0 + 4 * (lane / 16) + j;
-                    if (r < rows) z[r] = (ZT)(tau[3 * (r % B) + 2] * (double)(part[j] + c4));
+                    for (int nt = 0; nt < D / 16; ++nt)
+                        store4<G>(Y + r * D + nt * 16 + 4 * (lane / 16), relu(o[nt][0]),
+                                  relu(o[nt][1]), relu(o[nt][2]), relu(o[nt][3]));
                 }
+            } else {
+                // ---- decoder on the tile: Y -> LDS (row-major, K padded to
+                // KP with zeros), hidden^T = W3^T Y^T, then ReLU(. + c3) W4
+                constexpr int KP = (sizeof(G) == 2) ? ((D + 31) / 32) * 32 : D;
+                wave_lds_sync();  // every lane has read its tile fragments
+#pragma unroll
+                for (int nt = 0; nt < D / 16; ++nt) {
+                    const int f = nt * 16 + 4 * (lane / 16);
+                    store4<mt>(&As[wv][lane % 16][f], relu(o[nt][0]), relu(o[nt][1]),
+                               relu(o[nt][2]), relu(o[nt][3]));
+                    if constexpr (KP > D) store4<mt>(&As[wv][lane % 16][D + f], 0.f, 0.f, 0.f, 0.f);
+                }
+                wave_lds_sync();
+                f32x4 hacc[H / 16];
+#pragma unroll
+                for (int nt = 0; nt < H / 16; ++nt) hacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (sizeof(G) == 4) {
+                    const float *pk = (const float *)w3;
+#pragma unroll 4
+                    for (int ks = 0; ks < D / 4; ++ks) {
+                        const float a = As[wv][lane % 16][ks * 4 + lane / 16];
+#pragma unroll
+                        for (int nt = 0; nt < H / 16; ++nt)
+                            hacc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                pk[(ks * (H / 16) + nt) * 64 + lane], a, hacc[nt], 0, 0, 0);
+                    }
+                } else {
+                    const uint16_t *pk = (const uint16_t *)w3;
+#pragma unroll
+                    for (int kb = 0; kb < KP / 32; ++kb) {
+                        const bf16x8 yf = load_bf16x8(&As[wv][lane % 16][kb * 32 + 8 * (lane / 16)]);
+#pragma unroll
+                        for (int nt = 0; nt < H / 16; ++nt)
+                            hacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                load_bf16x8(pk + ((int64_t)(kb * (H / 16) + nt) * 64 + lane) * 8),
+                                yf, hacc[nt], 0, 0, 0);
+                    }
+                }
+                // lane holds hidden units nt*16 + 4 (l/16) + j of row l % 16
+                const float *c3 = vec + oc3, *W4 = vec + oW4;
+                float part = 0.f;
+#pragma unroll
+                for (int nt = 0; nt < H / 16; ++nt) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = nt * 16 + 4 * (lane / 16) + j;
+                        part += fmaxf(hacc[nt][j] + c3[k], 0.f) * W4[k];
+                    }
+                }
+                part += __shfl_xor(part, 16, WAVE);
+                part += __shfl_xor(part, 32, WAVE);
+                if (lane < 16 && r < rows)
+                    z[r] = (ZT)(tau[3 * (r % B) + 2] * (double)(part + vec[oc4]));
             }
         }
+        // ---- rotate the prefetched CSR state; every lane is done with this
+        // tile's LDS before the next commit
+        wave_lds_sync();
+        rpv = rpn;
+        kbeg = kbeg_n;
+        cnt = cnt_n;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            cv[u] = cv_n[u];
+            av[u] = av_n[u];
+        }
     }
+}
+
+// Grid of the persistent layer kernel: as many blocks as can be resident at
+// once (occupancy x compute units), at most one 64-row block per tile group.
+template <typename G, int D, int H, bool DEC, typename ZT>
+inline int layer_grid(int64_t rows) {
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_layer<G, D, H, DEC, ZT>,
+                                                           BLOCK, 0);
+        resident = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+    }
+    const int64_t need = (rows + 63) / 64;
+    return (int)(need < resident ? need : resident);
 }
 
 }  // namespace gnp

@@ -100,7 +100,19 @@ CASES = {
     "convdiff3d_16_d32": (lambda: I.convdiff3d(16), 8, 32, 64),
     "powerlaw_20000_d32": (lambda: I.powerlaw_random(20000, seed_structure=9, seed_values=10),
                            8, 32, 64),
+    "empty_tail_rows": (lambda: _with_empty_rows(), 2, 32, 64),
 }
+
+
+def _with_empty_rows():
+    """A matrix whose last 40 rows are empty (a valid CSR; the network's
+    sparse product is zero there)."""
+    A = I.convdiff3d(6)
+    n = A.n
+    keep = A.rowptr[n - 40]
+    rp = A.rowptr.copy()
+    rp[n - 40:] = keep
+    return I.CSR(n, rp, A.colind[:keep].copy(), A.val[:keep].copy(), "empty_tail")
 
 
 @pytest.mark.parametrize("case", list(CASES))
