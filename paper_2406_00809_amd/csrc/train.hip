@@ -9,14 +9,16 @@
 //   encoder:  E = ReLU(u W1 + c1) W2 + c2
 //   loss:     l = mean |A z - b|, dl/dz = A^T sign(A z - b) / (n B)
 // Weight gradients are sums over all rows: every block keeps its own sums
-// over a fixed set of 64-row tiles and writes one partial per parameter;
-// one kernel then adds the partials in block order (deterministic).
+// over a fixed set of row tiles and writes one partial per parameter; one
+// kernel then adds the partials in block order (deterministic).  The FP32
+// backward runs on MFMA (bwd_mfma.hpp); FP64 uses the VALU kernels below.
 // The whole training loop is stream-ordered with no host synchronisation.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
 
+#include "bwd_mfma.hpp"
 #include "gnp_fwd.hpp"
 #include "model.hpp"
 
@@ -599,20 +601,40 @@ static void bwd(gnp_model *m, TrainCtx *c, const T *bin, const T *dz, hipStream_
     T *acts = (T *)c->acts;
     T *dA = (T *)c->dA, *dB = (T *)c->dB, *G = (T *)c->G;
     const int nbg = c->nbg;
-    hipLaunchKernelGGL((k_dec_bwd<T, D, H>), dim3(nbg), dim3(BLOCK), 0, st, rows, B,
-                       acts + (int64_t)m->L * rows * D, dz, th, po.W3, po.c3, po.W4, po.c4,
-                       (const double *)c->tau, dA, c->gpart, m->np);
+    // FP32: MFMA kernels; FP64: VALU kernels (reference precision)
+    constexpr bool MF = sizeof(T) == 4;
+    if constexpr (MF)
+        hipLaunchKernelGGL((k_dec_bwd_mfma<D, H>), dim3(nbg), dim3(BLOCK), 0, st, rows, B,
+                           acts + (int64_t)m->L * rows * D, dz, th, po.W3, po.c3, po.W4, po.c4,
+                           (const double *)c->tau, dA, c->gpart, m->np);
+    else
+        hipLaunchKernelGGL((k_dec_bwd<T, D, H>), dim3(nbg), dim3(BLOCK), 0, st, rows, B,
+                           acts + (int64_t)m->L * rows * D, dz, th, po.W3, po.c3, po.W4, po.c4,
+                           (const double *)c->tau, dA, c->gpart, m->np);
     for (int l = m->L - 1; l >= 0; --l) {
         const int64_t oU = po.U0 + (int64_t)l * 2 * D * D;
-        hipLaunchKernelGGL((k_layer_bwd1<T, D>), dim3(nbg), dim3(BLOCK), 0, st, rows, B, s->rp,
-                           s->ci, ahat, acts + (int64_t)l * rows * D,
-                           acts + (int64_t)(l + 1) * rows * D, dA, th, oU, G, dB, c->gpart, m->np);
+        if constexpr (MF)
+            hipLaunchKernelGGL((k_layer_bwd1_mfma<D>), dim3(nbg), dim3(BLOCK), 0, st, rows, B,
+                               s->rp, s->ci, ahat, acts + (int64_t)l * rows * D,
+                               acts + (int64_t)(l + 1) * rows * D, dA, th, oU, G, dB, c->gpart,
+                               m->np);
+        else
+            hipLaunchKernelGGL((k_layer_bwd1<T, D>), dim3(nbg), dim3(BLOCK), 0, st, rows, B,
+                               s->rp, s->ci, ahat, acts + (int64_t)l * rows * D,
+                               acts + (int64_t)(l + 1) * rows * D, dA, th, oU, G, dB, c->gpart,
+                               m->np);
         hipLaunchKernelGGL((k_layer_bwd2<T, D>), dim3(grid_for(rows * 4, BLOCK)), dim3(BLOCK), 0,
                            st, rows, B, s->trp, s->tci, tahat, G, dB);
         std::swap(dA, dB);
     }
-    hipLaunchKernelGGL((k_enc_bwd<T, D, H>), dim3(nbg), dim3(BLOCK), 0, st, rows, B, bin,
-                       (const double *)c->tau, th, po.W1, po.c1, po.W2, po.c2, dA, c->gpart, m->np);
+    if constexpr (MF)
+        hipLaunchKernelGGL((k_enc_bwd_mfma<D, H>), dim3(nbg), dim3(BLOCK), 0, st, rows, B, bin,
+                           (const double *)c->tau, th, po.W1, po.c1, po.W2, po.c2, dA, c->gpart,
+                           m->np);
+    else
+        hipLaunchKernelGGL((k_enc_bwd<T, D, H>), dim3(nbg), dim3(BLOCK), 0, st, rows, B, bin,
+                           (const double *)c->tau, th, po.W1, po.c1, po.W2, po.c2, dA, c->gpart,
+                           m->np);
     hipLaunchKernelGGL(k_grad_reduce, dim3(grid_for(m->np, BLOCK)), dim3(BLOCK), 0, st, m->np,
                        nbg, c->gpart, c->grad);
 }

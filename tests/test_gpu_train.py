@@ -37,6 +37,10 @@ GRAD_CASES = {
     "convdiff3d_8_d32": (lambda: I.convdiff3d(8), 4, 32, 64, 3),
     "powerlaw_3000_d32": (lambda: I.powerlaw_random(3000, seed_structure=3, seed_values=4),
                           2, 32, 64, 2),
+    # rows (nodes x batch) not a multiple of the 16-row tile
+    "ragged_laplace2d_13_d16": (lambda: I.laplace2d(13), 2, 16, 32, 3),
+    # fewer rows than one tile
+    "tiny_laplace2d_3_d32": (lambda: I.laplace2d(3), 1, 32, 64, 1),
 }
 
 
