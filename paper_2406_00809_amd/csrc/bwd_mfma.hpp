@@ -1,4 +1,5 @@
-// FP32 backward kernels of the network on MFMA (v_mfma_f32_16x16x4_f32).
+// FP32 training kernels of the network on MFMA (v_mfma_f32_16x16x4_f32):
+// the decoder forward and the backward of decoder, layers and encoder.
 //
 // Each wavefront walks 16-row tiles (tile stride = wavefronts in the grid)
 // with LDS regions of its own.  Weight gradients are sums over rows of outer
@@ -54,6 +55,36 @@ __device__ __forceinline__ void wt_tile(const float *Wm, int ldw, const float *T
         for (int pt = 0; pt < P / 16; ++pt)
             out[pt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Wm[(pt * 16 + lane % 16) * ldw + k], b,
                                                           out[pt], 0, 0, 0);
+    }
+}
+
+// acc += sum over k in [k0, k1) of av[k] * X[(ci[k] * B + b) * NF*4 + q * NF + e]
+// for the lane's NF features.  Neighbour indices and values are fetched NB at
+// a time (clamped, unconditional loads), so NB row loads are in flight at once
+// instead of a dependent index -> row chain per neighbour; the sum is taken in
+// k order.
+template <typename T, int NF, int NB>
+__device__ __forceinline__ void gather_rows(const int32_t *__restrict__ ci,
+                                            const T *__restrict__ av, int32_t k0, int32_t k1,
+                                            const T *__restrict__ X, uint32_t B, uint32_t b,
+                                            int q, T (&acc)[NF]) {
+    for (int32_t kb = k0; kb < k1; kb += NB) {
+        uint32_t c[NB];
+        T a[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int32_t k = kb + u < k1 ? kb + u : k1 - 1;
+            c[u] = (uint32_t)ci[k];
+            a[u] = kb + u < k1 ? av[k] : (T)0;
+        }
+        T nv[NB][NF];
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            load_feats<T, NF>(X + (c[u] * B + b) * (uint32_t)(4 * NF) + q * NF, nv[u]);
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+#pragma unroll
+            for (int e = 0; e < NF; ++e) acc[e] += a[u] * nv[u][e];
     }
 }
 
@@ -124,6 +155,72 @@ __device__ __forceinline__ void flush_scalar(float v, float *buf, double *gp, in
     __syncthreads();
     if (threadIdx.x == 0) gp[off] = (double)(((buf[0] + buf[1]) + buf[2]) + buf[3]);
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Decoder forward of training (reads the saved X_L):
+//   z = (tau / sqrt n) (ReLU(X_L W3 + c3) W4 + c4)   (Eq. (6))
+// ---------------------------------------------------------------------------
+template <int D, int H>
+__global__ __launch_bounds__(BLOCK) void k_dec_fwd_mfma(int64_t rows, int B,
+                                                        const float *__restrict__ X,
+                                                        const float *__restrict__ th, int64_t oW3,
+                                                        int64_t oc3, int64_t oW4, int64_t oc4,
+                                                        const double *__restrict__ tau,
+                                                        float *__restrict__ z) {
+    constexpr int LX = ldp<D>(), LH = ldp<H>();
+    __shared__ float smem[4 * 16 * LX];
+    __shared__ float W3s[D * LH];  // W3[f][k]
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    float *Xs = smem + wv * 16 * LX;
+    for (int e = threadIdx.x; e < D * H; e += BLOCK) W3s[(e / H) * LH + e % H] = th[oW3 + e];
+    __syncthreads();
+    float c3r[H / 16][4], w4r[H / 16][4];
+#pragma unroll
+    for (int kt = 0; kt < H / 16; ++kt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            c3r[kt][j] = th[oc3 + kt * 16 + 4 * (lane / 16) + j];
+            w4r[kt][j] = th[oW4 + kt * 16 + 4 * (lane / 16) + j];
+        }
+    const float c4 = th[oc4];
+    const int64_t ntiles = (rows + 15) / 16, nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    for (int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv; t < ntiles; t += nw) {
+        const int64_t r0 = t * 16;
+        {
+            const int rl = lane / 4, q = lane % 4;
+            const int64_t r = r0 + rl;
+            float xv[D / 4];
+#pragma unroll
+            for (int e = 0; e < D / 4; ++e) xv[e] = 0.f;
+            if (r < rows) load_feats<float, D / 4>(X + r * D + q * (D / 4), xv);
+#pragma unroll
+            for (int e = 0; e < D / 4; ++e) Xs[rl * LX + q * (D / 4) + e] = xv[e];
+        }
+        wave_lds_sync();
+        f32x4 pre[H / 16];
+#pragma unroll
+        for (int kt = 0; kt < H / 16; ++kt) pre[kt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int ks = 0; ks < D / 4; ++ks) {
+            const int f = 4 * ks + lane / 16;
+            const float b = Xs[(lane % 16) * LX + f];
+#pragma unroll
+            for (int kt = 0; kt < H / 16; ++kt)
+                pre[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(W3s[f * LH + kt * 16 + lane % 16], b,
+                                                              pre[kt], 0, 0, 0);
+        }
+        float part = 0.f;
+#pragma unroll
+        for (int kt = 0; kt < H / 16; ++kt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) part += fmaxf(pre[kt][j] + c3r[kt][j], 0.f) * w4r[kt][j];
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        const int64_t r = r0 + lane;
+        if (lane < 16 && r < rows) z[r] = (float)(tau[3 * (r % B) + 2] * (double)(part + c4));
+        wave_lds_sync();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -282,16 +379,8 @@ __global__ __launch_bounds__(BLOCK) void k_layer_bwd1_mfma(
                 load_feats<float, D / 4>(X + r * D + q * (D / 4), xv);
                 load_feats<float, D / 4>(Y + r * D + q * (D / 4), yv);
                 load_feats<float, D / 4>(dY + r * D + q * (D / 4), gv);
-                const int32_t ke = rp[i + 1];
-                for (int32_t k = rp[i]; k < ke; ++k) {
-                    const uint32_t c = (uint32_t)ci[k];
-                    const float a = ahat[k];
-                    float nv[D / 4];
-                    load_feats<float, D / 4>(
-                        X + (c * (uint32_t)B + (uint32_t)b) * (uint32_t)D + q * (D / 4), nv);
-#pragma unroll
-                    for (int e = 0; e < D / 4; ++e) tv[e] += a * nv[e];
-                }
+                gather_rows<float, D / 4, 4>(ci, ahat, rp[i], rp[i + 1], X, (uint32_t)B,
+                                             (uint32_t)b, q, tv);
             }
 #pragma unroll
             for (int e = 0; e < D / 4; ++e) {

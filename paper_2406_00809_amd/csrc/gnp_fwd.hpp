@@ -190,8 +190,8 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
 // -> ReLU -> store.  With DEC the output tile stays in LDS and feeds the
 // decoder  o = ReLU(Y W3 + c3) W4 + c4,  z = (tau/sqrt(n)) o  (Eq. (6)).
 //
-// Persistent, software-pipelined walk over 16-row tiles (stride = number of
-// wavefronts in the grid).  Tile t touches nodes ifirst..ilast whose nonzeros
+// Persistent, software-pipelined walk over 16-row tiles (XCD-aware order,
+// see xcd_walk).  Tile t touches nodes ifirst..ilast whose nonzeros
 // are contiguous in CSR; that slice (colind, values, rowptr offsets) is
 // staged in the wavefront's LDS.  The rowptr slice of the next tile is
 // requested before the gathers of the current one, and its colind / value
@@ -216,8 +216,8 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
     __shared__ int32_t sCi[BLOCK / WAVE][CAP];
     __shared__ vt_t sVa[BLOCK / WAVE][CAP];
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    const int64_t ntiles = (rows + 15) / 16;
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv);
+    const int64_t ntiles = walk.end, nw = walk.stride;
 
     auto node_range = [&](int64_t t, int64_t &ifirst, int &nn) {
         const int64_t r0 = t * 16;
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
         }
     };
 
-    int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
+    int64_t t = walk.t;
     int32_t rpv = 0, kbeg = 0, cnt = 0;
     int32_t cv[NC];
     vt_t av[NC];
@@ -494,7 +494,8 @@ inline int layer_grid(int64_t rows) {
         resident = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
     }
     const int64_t need = (rows + 63) / 64;
-    return (int)(need < resident ? need : resident);
+    int g = (int)(need < resident ? need : resident);
+    return g >= XCDS ? g - g % XCDS : g;  // whole rounds over the XCDs
 }
 
 }  // namespace gnp

@@ -94,6 +94,36 @@ __device__ __forceinline__ bool last_block(unsigned *counter) {
 // ---------------------------------------------------------------------------
 // precision selection
 // ---------------------------------------------------------------------------
+// Tile walk of a persistent grid that keeps every XCD on one contiguous range
+// of tiles.  MI355X dispatches workgroups to its 8 XCDs round-robin (block b
+// runs on XCD b % 8), and each XCD has an L2 of its own: with XCD x taking
+// tiles [x T/8, (x+1) T/8) and its wavefronts striding through that range,
+// the rows a tile gathers from its graph neighbours were mostly brought into
+// that XCD's L2 by nearby tiles.  The walk covers every tile exactly once for
+// any grid (grids that are not a multiple of 8 fall back to a plain stride);
+// the placement only affects speed.
+constexpr int XCDS = 8;
+struct TileWalk {
+    int64_t t, end, stride;
+};
+__device__ __forceinline__ TileWalk xcd_walk(int64_t ntiles, int waves_per_block, int wv) {
+    TileWalk w;
+    if (gridDim.x % XCDS == 0) {
+        const int64_t nbx = gridDim.x / XCDS;
+        const int64_t x = blockIdx.x % XCDS, lb = blockIdx.x / XCDS;
+        const int64_t per = (ntiles + XCDS - 1) / XCDS;
+        const int64_t beg = x * per;
+        w.end = beg + per < ntiles ? beg + per : ntiles;
+        w.t = beg + lb * waves_per_block + wv;
+        w.stride = nbx * waves_per_block;
+    } else {
+        w.t = (int64_t)blockIdx.x * waves_per_block + wv;
+        w.end = ntiles;
+        w.stride = (int64_t)gridDim.x * waves_per_block;
+    }
+    return w;
+}
+
 inline bool valid_precision(int p) { return p == GNP_F64 || p == GNP_F32 || p == GNP_BF16; }
 
 inline int grid_for(int64_t work, int per_block, int cap = 1 << 20) {

@@ -325,12 +325,8 @@ __global__ __launch_bounds__(BLOCK) void k_layer_bwd2(int64_t rows, int B,
     T acc[D / 4];
 #pragma unroll
     for (int e = 0; e < D / 4; ++e) acc[e] = dX[r * D + q * (D / 4) + e];
-    for (int32_t k = trp[i]; k < trp[i + 1]; ++k) {
-        const T a = tahat[k];
-        const T *gs = G + ((int64_t)tci[k] * B + b) * D + q * (D / 4);
-#pragma unroll
-        for (int e = 0; e < D / 4; ++e) acc[e] += a * gs[e];
-    }
+    gather_rows<T, D / 4, sizeof(T) == 8 ? 4 : 8>(tci, tahat, trp[i], trp[i + 1], G,
+                                                  (uint32_t)B, (uint32_t)b, q, acc);
 #pragma unroll
     for (int e = 0; e < D / 4; ++e) dX[r * D + q * (D / 4) + e] = acc[e];
 }
@@ -584,9 +580,14 @@ static void fwd_save(gnp_model *m, TrainCtx *c, const T *bin, T *z, hipStream_t 
                            (const int *)nullptr);
     }
     const int gd = (int)std::min<int64_t>(4096, (rows + TB - 1) / TB);
-    hipLaunchKernelGGL((k_dec_fwd<T, D, H>), dim3(gd), dim3(BLOCK), 0, st, rows, B,
-                       acts + (int64_t)m->L * rows * D, vec, po.W3, po.c3, po.W4, po.c4,
-                       (const double *)c->tau, z);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_dec_fwd_mfma<D, H>), dim3(gd), dim3(BLOCK), 0, st, rows, B,
+                           acts + (int64_t)m->L * rows * D, vec, po.W3, po.c3, po.W4, po.c4,
+                           (const double *)c->tau, z);
+    else
+        hipLaunchKernelGGL((k_dec_fwd<T, D, H>), dim3(gd), dim3(BLOCK), 0, st, rows, B,
+                           acts + (int64_t)m->L * rows * D, vec, po.W3, po.c3, po.W4, po.c4,
+                           (const double *)c->tau, z);
 }
 
 template <typename T, int D, int H>
