@@ -11,11 +11,13 @@ preconditioner, float64 Arnoldi dots/norms, Givens and true residual,
 float32 SpMV and basis, network in bf16 on MFMA (and float32 for
 comparison).  One step = one whole solve from x0 = 0 to rtol 1e-8.
 
-Prints one JSON line (see the contract in the design doc).
+Prints one JSON line with the metric, the roofline figures of the dominant
+kernel and the oracle's host-core baseline.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -57,6 +59,26 @@ def cpu_baseline(A, th, arch, gpu_iters, sample_iters):
     }
 
 
+def layer_traffic(prec):
+    """HBM bytes per launch of the BF16 layer kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since the counters were taken (or for another precision)."""
+    if prec != "bf16":
+        return None
+    here = os.path.dirname(os.path.abspath(__file__))
+    summ = os.path.join(here, "profiles", "k_layer_bf16_convdiff3d_64_hbm_counters.md")
+    src = os.path.join(here, "paper_2406_00809_amd", "csrc", "gnp_fwd.hpp")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(summ).read().splitlines()
+                      if line.startswith("traffic_"))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if fields.get("traffic_source_sha256", "").strip() != digest:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,7 +101,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of this path is described in DESIGN.md but not built.", file=sys.stderr)
+              "sharding of this path is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -233,7 +255,7 @@ def main():
             "peak": 8000.0,
             "unit": "GB/s",
             "frac": achieved / 8000.0,
-            "traffic": None,
+            "traffic": layer_traffic(args.prec),
             "avg_us": 1e3 * lay_ms,
             "algorithmic_bytes": layer_bytes,
         },
