@@ -230,6 +230,81 @@ GNP_API gnp_status gnp_backward(gnp_model *model, const void *dz_dev, double *dp
                                 void *hip_stream);
 
 /* ------------------------------------------------------------------------ */
+/* Solve server: continuous batching over resident systems                   */
+/* ------------------------------------------------------------------------ */
+
+/* The paper applies one trained preconditioner to any number of right-hand
+ * sides of its system (Sec. 2.2 trains on a distribution of b).  The server
+ * keeps registered systems (CSR, A-hat) and their networks resident and
+ * solves a stream of requests, each one FGMRES(m) from x0 = 0 exactly as
+ * fgmres_solve runs it (same kernels, buffers of its own), so a result does
+ * not depend on the other requests in flight.
+ *
+ * A worker thread admits queued requests into up to max_slots slots whenever
+ * a slot and HBM free up (continuous batching): each slot needs a solve
+ * workspace for its system (Krylov basis, network outputs and activations,
+ * b, x; gnp_server_workspace_bytes), and the workspaces held never exceed
+ * hbm_budget bytes.  A finished request leaves its workspace resident for the
+ * next request on the same system; idle workspaces of other systems are
+ * evicted, least recently used first, when a new one would not fit.  A request
+ * whose workspace alone exceeds the budget fails with GNP_ENOMEM.  Requests
+ * that fit may overtake one that waits for memory, at most 8 while the same
+ * request heads the queue.  Every slot has its own HIP stream, so the solves
+ * in flight overlap on the device.
+ *
+ * Latency of a request: from gnp_server_submit to the moment its solution is
+ * in host memory.  All server entry points are thread-safe. */
+typedef struct gnp_server gnp_server;
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected; /* rejected: larger than the budget */
+    int64_t queued, active, max_active;             /* requests waiting / in slots now / peak */
+    double latency_p50_s, latency_p99_s, latency_mean_s; /* completed requests, nearest rank */
+    double solves_per_s;  /* completed / (last completion - first submission) */
+    size_t hbm_budget, hbm_used, hbm_peak; /* bytes of solve workspaces held */
+    int64_t workspaces_allocated, workspaces_reused, workspaces_evicted;
+} gnp_server_stats;
+
+/* Start a server on the current device.  m: restart length of every solve
+ * (1..255); max_iters: largest maxiters a request may ask for; prec: the
+ * network / Krylov precision (as in fgmres_solve).
+ * Errors: GNP_EINVAL for max_slots outside [1, 256], bad m, max_iters < 1,
+ * hbm_budget = 0 or a bad precision; GNP_EDEVICE if streams cannot be made. */
+GNP_API gnp_status gnp_server_create(size_t hbm_budget, int max_slots, int m, int max_iters,
+                                     gnp_precision prec, gnp_server **out);
+
+/* Register a system and its network (model = NULL: unpreconditioned GMRES).
+ * Both must outlive the server.  *id receives the system's id. */
+GNP_API gnp_status gnp_server_register(gnp_server *srv, gnp_system *sys, gnp_model *model,
+                                       int *id);
+
+/* Device bytes one solve workspace of system `id` takes. */
+GNP_API gnp_status gnp_server_workspace_bytes(gnp_server *srv, int id, size_t *bytes);
+
+/* Queue a solve of A_id x = b: b_host (host, n doubles) is copied before the
+ * call returns.  rtol > 0, 1 <= maxiters <= max_iters.  *ticket identifies
+ * the request for gnp_server_poll. */
+GNP_API gnp_status gnp_server_submit(gnp_server *srv, int id, const double *b_host, double rtol,
+                                     int maxiters, uint64_t *ticket);
+
+/* Collect a request: GNP_EBUSY while it is queued or running; otherwise the
+ * request's own status (GNP_OK, or the error that ended it), and the ticket is
+ * released.  On GNP_OK: x_host (n doubles), info and latency_s (seconds from
+ * submission to completion) are filled (each may be NULL). */
+GNP_API gnp_status gnp_server_poll(gnp_server *srv, uint64_t ticket, double *x_host,
+                                   gnp_solve_info *info, double *latency_s);
+
+/* Block until no request is queued or running, or until timeout_s seconds
+ * have passed (GNP_EBUSY). */
+GNP_API gnp_status gnp_server_drain(gnp_server *srv, double timeout_s);
+
+GNP_API gnp_status gnp_server_get_stats(gnp_server *srv, gnp_server_stats *out);
+
+/* Stop the server: requests still queued fail with GNP_EBUSY, running ones
+ * finish first; uncollected results are dropped. */
+GNP_API void gnp_server_destroy(gnp_server *srv);
+
+/* ------------------------------------------------------------------------ */
 /* Measurement helpers                                                      */
 /* ------------------------------------------------------------------------ */
 

@@ -39,6 +39,20 @@ class SolveInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("rejected", C.c_int64), ("queued", C.c_int64), ("active", C.c_int64),
+                ("max_active", C.c_int64), ("latency_p50_s", C.c_double),
+                ("latency_p99_s", C.c_double), ("latency_mean_s", C.c_double),
+                ("solves_per_s", C.c_double), ("hbm_budget", C.c_size_t),
+                ("hbm_used", C.c_size_t), ("hbm_peak", C.c_size_t),
+                ("workspaces_allocated", C.c_int64), ("workspaces_reused", C.c_int64),
+                ("workspaces_evicted", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 SIGNATURES = {
     "gnp_last_error": (C.c_char_p, []),
     "gnp_version": (C.c_char_p, []),
@@ -65,6 +79,16 @@ SIGNATURES = {
     "gnp_backward": (C.c_int, [VP, VP, VP, VP]),
     "gnp_time_layer": (C.c_int, [VP, C.c_int, C.c_int, C.c_int, F64P, VP]),
     "gnp_time_spmv": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, F64P, VP]),
+    "gnp_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_int, C.c_int, C.c_int,
+                                    C.POINTER(VP)]),
+    "gnp_server_register": (C.c_int, [VP, VP, VP, C.POINTER(C.c_int)]),
+    "gnp_server_workspace_bytes": (C.c_int, [VP, C.c_int, C.POINTER(C.c_size_t)]),
+    "gnp_server_submit": (C.c_int, [VP, C.c_int, VP, C.c_double, C.c_int,
+                                    C.POINTER(C.c_uint64)]),
+    "gnp_server_poll": (C.c_int, [VP, C.c_uint64, VP, C.POINTER(SolveInfo), F64P]),
+    "gnp_server_drain": (C.c_int, [VP, C.c_double]),
+    "gnp_server_get_stats": (C.c_int, [VP, C.POINTER(ServerStats)]),
+    "gnp_server_destroy": (None, [VP]),
 }
 
 _lib = None

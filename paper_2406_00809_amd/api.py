@@ -210,3 +210,73 @@ def fgmres_solve(system: System, b: torch.Tensor, model: Model | None = None,
     if hist is not None:
         hist = hist[: d["iters"] + 1]
     return x, d, hist
+
+
+class Server:
+    """Continuous-batching solve server (gnp_server_*): requests for any
+    registered system are admitted into slots as slots and HBM free up and
+    solved concurrently on the device; results are collected by ticket."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 16, m: int = 30,
+                 max_iters: int = 3000, prec="bf16"):
+        h = C.c_void_p()
+        check(_lib.load().gnp_server_create(int(hbm_budget), int(max_slots), int(m),
+                                            int(max_iters), PREC[prec], C.byref(h)))
+        self._h = h
+        self._n = {}
+        self._keep = []  # systems / models must outlive the server
+
+    def register(self, system: System, model: Model | None = None) -> int:
+        i = C.c_int()
+        check(_lib.load().gnp_server_register(self._h, system.handle,
+                                              model.handle if model is not None else None,
+                                              C.byref(i)))
+        self._n[i.value] = system.n
+        self._keep.append((system, model))
+        return i.value
+
+    def workspace_bytes(self, sid: int) -> int:
+        b = C.c_size_t()
+        check(_lib.load().gnp_server_workspace_bytes(self._h, int(sid), C.byref(b)))
+        return b.value
+
+    def submit(self, sid: int, b, rtol: float = 1e-8, maxiters: int = 3000) -> int:
+        arr, ptr = _host(b, np.float64)
+        if arr.size != self._n[sid]:
+            raise ValueError(f"b must have {self._n[sid]} entries")
+        t = C.c_uint64()
+        check(_lib.load().gnp_server_submit(self._h, int(sid), ptr, float(rtol), int(maxiters),
+                                            C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, n: int):
+        """(x, info dict, latency seconds), or None while the request runs."""
+        x = np.empty(n, dtype=np.float64)
+        info = SolveInfo()
+        lat = C.c_double()
+        st = _lib.load().gnp_server_poll(self._h, C.c_uint64(ticket),
+                                         x.ctypes.data_as(C.c_void_p), C.byref(info),
+                                         C.byref(lat))
+        if st == _lib.GNP_EBUSY:
+            return None
+        check(st)
+        return x, info.as_dict(), lat.value
+
+    def drain(self, timeout_s: float = 600.0):
+        check(_lib.load().gnp_server_drain(self._h, float(timeout_s)))
+
+    def stats(self) -> dict:
+        s = _lib.ServerStats()
+        check(_lib.load().gnp_server_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().gnp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

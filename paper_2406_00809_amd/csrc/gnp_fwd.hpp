@@ -484,15 +484,14 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
 // once (occupancy x compute units), at most one 64-row block per tile group.
 template <typename G, int D, int H, bool DEC, typename ZT>
 inline int layer_grid(int64_t rows) {
-    static int resident = 0;
-    if (resident == 0) {
+    static const int resident = [] {  // initialised once, thread-safe
         int dev = 0, cus = 0, per_cu = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_layer<G, D, H, DEC, ZT>,
                                                            BLOCK, 0);
-        resident = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
-    }
+        return (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+    }();
     const int64_t need = (rows + 63) / 64;
     int g = (int)(need < resident ? need : resident);
     return g >= XCDS ? g - g % XCDS : g;  // whole rounds over the XCDs

@@ -521,6 +521,19 @@ void solve_ctx_free(SolveCtx *c) {
     *c = SolveCtx();
 }
 
+size_t solve_ctx_bytes(int64_t n, int m, int maxiters, gnp_precision prec, int act_d) {
+    const size_t kb = (prec == GNP_F64) ? 8 : 4;
+    const int mp = basis_pitch(m);
+    const int64_t cap = std::max(maxiters, 128);
+    const int64_t nb_cgs = (n + cgs_rpb(n) - 1) / cgs_rpb(n);
+    const int64_t npartial = std::max<int64_t>(nb_cgs * (mp + 1), 2048);
+    size_t b = kb * (size_t)n * (mp + m + 2) + sizeof(double) * n;
+    if (act_d > 0) b += 2 * sizeof(double) * (size_t)n * act_d;
+    b += sizeof(double) * (4 + 2 * (m + 1) * m + 3 * m + 3 * (m + 1) + cap + 1 + npartial);
+    b += sizeof(Ctl);
+    return b;
+}
+
 gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
                              gnp_precision prec, int act_d) {
     const size_t kb = (prec == GNP_F64) ? 8 : 4;
@@ -648,11 +661,9 @@ static void launch_residual(SolveCtx *c, const double *b, const double *x, int i
                        (const double *)c->partial, c->ctl, c->g, c->hist, initial);
 }
 
-gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, int m,
-                     double rtol, int maxiters, double *hist_host, gnp_solve_info *info,
-                     hipStream_t st) {
-    gnp_system *s = c->sys;
-    const int64_t n = s->n;
+gnp_status solve_begin(SolveCtx *c, const double *b, const double *x, int m, double rtol,
+                       int maxiters, hipStream_t st) {
+    const int64_t n = c->sys->n;
     Ctl init;
     memset(&init, 0, sizeof(init));
     init.m = m;
@@ -665,6 +676,36 @@ gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, 
                        rtol, c->ctl);
     launch_residual(c, b, x, 1, st);
     GNP_HIP(hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    return GNP_OK;
+}
+
+gnp_status solve_next(SolveCtx *c, gnp_model *model, const double *b, double *x, int m,
+                      int maxiters, hipStream_t st) {
+    const int it0 = c->ctl_host->it;
+    const int nsteps = std::min(m, maxiters - it0);
+    if (c->prec == GNP_F64) GNP_TRY(launch_cycle<double>(c, model, nsteps, x, st));
+    else GNP_TRY(launch_cycle<float>(c, model, nsteps, x, st));
+    launch_residual(c, b, x, 0, st);
+    GNP_HIP(hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    return GNP_OK;
+}
+
+void solve_info_from(const Ctl &h, gnp_solve_info *info) {
+    if (!info) return;
+    info->iters = h.it;
+    info->restarts = h.restarts;
+    info->converged = h.converged;
+    info->breakdowns = h.breakdowns;
+    info->rel_res_true = h.rel_true;
+    info->rel_res_est = h.est_rel;
+    info->mismatch = (h.est_rel > 0.0 && h.rel_true > 10.0 * h.est_rel) ? 1 : 0;
+}
+
+gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, int m,
+                     double rtol, int maxiters, double *hist_host, gnp_solve_info *info,
+                     hipStream_t st) {
+    const int64_t n = c->sys->n;
+    GNP_TRY(solve_begin(c, b, x, m, rtol, maxiters, st));
     GNP_HIP(hipStreamSynchronize(st));
     if (!std::isfinite(c->ctl_host->bnorm)) return fail(GNP_ENUMERIC, "b is not finite");
     if (c->ctl_host->bnorm == 0.0) {
@@ -679,11 +720,7 @@ gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, 
     }
     while (!c->ctl_host->solve_done) {
         const int it0 = c->ctl_host->it;
-        const int nsteps = std::min(m, maxiters - it0);
-        if (c->prec == GNP_F64) GNP_TRY(launch_cycle<double>(c, model, nsteps, x, st));
-        else GNP_TRY(launch_cycle<float>(c, model, nsteps, x, st));
-        launch_residual(c, b, x, 0, st);
-        GNP_HIP(hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        GNP_TRY(solve_next(c, model, b, x, m, maxiters, st));
         GNP_HIP(hipStreamSynchronize(st));
         if (c->ctl_host->it <= it0 && !c->ctl_host->solve_done)
             return fail(GNP_EDEVICE, "solver made no progress in a cycle");
@@ -691,15 +728,7 @@ gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, 
     const Ctl &h = *c->ctl_host;
     if (hist_host)
         GNP_HIP(hipMemcpy(hist_host, c->hist, sizeof(double) * (h.it + 1), hipMemcpyDeviceToHost));
-    if (info) {
-        info->iters = h.it;
-        info->restarts = h.restarts;
-        info->converged = h.converged;
-        info->breakdowns = h.breakdowns;
-        info->rel_res_true = h.rel_true;
-        info->rel_res_est = h.est_rel;
-        info->mismatch = (h.est_rel > 0.0 && h.rel_true > 10.0 * h.est_rel) ? 1 : 0;
-    }
+    solve_info_from(h, info);
     if (h.nonfinite) return fail(GNP_ENUMERIC, "non-finite value in the Arnoldi process");
     return GNP_OK;
 }

@@ -53,7 +53,21 @@ struct SolveCtx {
 
 gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
                              gnp_precision prec, int act_d);
+// Device bytes solve_ctx_prepare allocates for these arguments.
+size_t solve_ctx_bytes(int64_t n, int m, int maxiters, gnp_precision prec, int act_d);
 void solve_ctx_free(SolveCtx *c);
+
+// Stages of a solve, each enqueued on `st` without waiting; each ends with a
+// copy of the control block to c->ctl_host, valid once the stream has
+// reached that point.  solve_begin: ||b||, target and the initial residual;
+// solve_next: one restart cycle (<= m Arnoldi steps, update of x, true
+// residual).  The caller stops when ctl_host->solve_done is set (or b = 0,
+// or ||b|| is not finite after solve_begin).
+gnp_status solve_begin(SolveCtx *c, const double *b, const double *x, int m, double rtol,
+                       int maxiters, hipStream_t st);
+gnp_status solve_next(SolveCtx *c, gnp_model *model, const double *b, double *x, int m,
+                      int maxiters, hipStream_t st);
+void solve_info_from(const Ctl &h, gnp_solve_info *info);
 
 // Enqueue the whole solve on `st` and run it to completion (one host sync per
 // cycle).  x holds x0 on entry.
