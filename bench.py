@@ -81,6 +81,132 @@ def layer_traffic(prec):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def serve_bench(args):
+    """Serving workload: a fleet of resident systems of four families with
+    log-uniform sizes, each with a trained network; Poisson arrivals of solve
+    requests for uniformly chosen systems; continuous batching in the server.
+    Saturation throughput (all requests queued at once) first, then a sweep of
+    arrival rates below and above it, and the same requests solved one at a
+    time with the float32 network for comparison."""
+    import math
+
+    import numpy as np
+    import torch
+    from paper_2406_00809_amd import api
+    from paper_2406_00809_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    L, d, h, m, rtol = 8, 32, 64, 30, 1e-8
+    rng = np.random.default_rng(6)
+    fams = ["laplace2d", "laplace3d", "convdiff3d", "powerlaw"]
+    fleet = []
+    t0 = time.perf_counter()
+    for k in range(args.serve_systems):
+        fam = fams[k % 4]
+        nt = math.exp(rng.uniform(math.log(4096), math.log(args.serve_nmax)))
+        if fam == "laplace2d":
+            A = I.laplace2d(max(8, round(nt ** 0.5)))
+        elif fam == "laplace3d":
+            A = I.laplace3d(max(4, round(nt ** (1 / 3))))
+        elif fam == "convdiff3d":
+            A = I.convdiff3d(max(4, round(nt ** (1 / 3))))
+        else:
+            A = I.powerlaw_random(int(nt), seed_structure=100 + k, seed_values=200 + k)
+        S = api.System(A)
+        M = api.Model(S, L, d, h, I.init_params(L, d, h, 300 + k))
+        M.train(args.serve_train_steps, 16, lr=1e-3, seed=400 + k, prec="f32")
+        fleet.append((f"{fam}_n{A.n}", A, S, M))
+    torch.cuda.synchronize()
+    log(f"fleet of {len(fleet)} systems trained in {time.perf_counter() - t0:.1f}s: "
+        + ", ".join(f[0] for f in fleet))
+
+    nreq = args.serve_requests
+    pick = np.random.default_rng(8).integers(0, len(fleet), nreq)
+    bs = [I.rhs_normal(fleet[s][1].n, 1000 + i) for i, s in enumerate(pick)]
+
+    def run(rate):
+        """Submit the requests (all at once when rate is None, else Poisson
+        arrivals at `rate` per second); return throughput and latencies."""
+        srv = api.Server(args.serve_budget_gb << 30, args.serve_slots, m, args.maxiters,
+                         prec=args.prec)
+        ids = [srv.register(S, M) for _, _, S, M in fleet]
+        gaps = np.random.default_rng(7).exponential(1.0 / rate, nreq) if rate else np.zeros(nreq)
+        tickets = {}
+        t_start = time.perf_counter()
+        t_next = t_start
+        for i in range(nreq):
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
+            tickets[srv.submit(ids[pick[i]], bs[i], rtol=rtol, maxiters=args.maxiters)] = i
+        srv.drain(3600.0)
+        wall = time.perf_counter() - t_start
+        conv, its = 0, []
+        for t, i in tickets.items():
+            x, info, lat = srv.poll(t, fleet[pick[i]][1].n)
+            conv += info["converged"]
+            its.append(info["iters"])
+        st = srv.stats()
+        srv.close()
+        return {"offered_per_s": rate, "solves_per_s": nreq / wall,
+                "latency_p50_ms": 1e3 * st["latency_p50_s"],
+                "latency_p99_ms": 1e3 * st["latency_p99_s"],
+                "converged": conv, "requests": nreq, "mean_iters": float(np.mean(its)),
+                "max_active": st["max_active"], "hbm_peak_gb": st["hbm_peak"] / 2 ** 30,
+                "workspaces_reused": st["workspaces_reused"],
+                "workspaces_evicted": st["workspaces_evicted"]}
+
+    sat = run(None)
+    log(f"saturation: {sat}")
+    sweep = []
+    for frac in (0.5, 0.7, 0.9, 1.1):
+        r = run(frac * sat["solves_per_s"])
+        log(f"offered {frac:.1f} x saturation: {r}")
+        sweep.append(r)
+
+    # the same requests one at a time, float32 network, fgmres_solve
+    t1 = time.perf_counter()
+    conv32 = 0
+    for i in range(nreq):
+        _, A, S, M = fleet[pick[i]]
+        b = torch.as_tensor(bs[i], dtype=torch.float64, device="cuda")
+        _, info, _ = api.fgmres_solve(S, b, M, m=m, rtol=rtol, maxiters=args.maxiters,
+                                      prec="f32", want_hist=False)
+        conv32 += info["converged"]
+    torch.cuda.synchronize()
+    seq32 = nreq / (time.perf_counter() - t1)
+    log(f"float32 single solves one at a time: {seq32:.2f} solves/s, {conv32} converged")
+
+    out = {
+        "metric": "served GNP-FGMRES solves/s to rtol 1e-8 (saturation), p50/p99 latency",
+        "value": sat["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": nreq,
+        "warmup": 0,
+        "ms_per_step": 1e3 / sat["solves_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"serving: {len(fleet)} resident systems (2D/3D Laplace, 3D "
+                         f"convection-diffusion, power-law random; n log-uniform in "
+                         f"[4096, {args.serve_nmax}]), GNP L={L} d={d} h={h} trained "
+                         f"{args.serve_train_steps} steps batch 16 each; {nreq} requests "
+                         f"b ~ N(0, I), uniform system choice; FGMRES({m}) rtol 1e-8, "
+                         f"{args.serve_slots} slots, HBM budget {args.serve_budget_gb} GiB"),
+            "systems": [f[0] for f in fleet],
+            "saturation": sat,
+            "poisson_sweep": sweep,
+            "fp32_single_solve_sequential_solves_per_s": seq32,
+            "fp32_single_solve_converged": conv32,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +224,14 @@ def main():
                     help="profiling mode: launch the layer kernel and the SpMV in the bench's "
                          "configuration plus a 256 MiB device copy (counter calibration), "
                          "no training or solves")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark: continuous batching over a fleet of systems")
+    ap.add_argument("--serve-systems", type=int, default=8)
+    ap.add_argument("--serve-nmax", type=int, default=500000)
+    ap.add_argument("--serve-train-steps", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-budget-gb", type=int, default=32)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the float32-network comparison solves")
     args = ap.parse_args()
@@ -105,6 +239,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is designed but not built.", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch

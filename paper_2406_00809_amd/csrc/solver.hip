@@ -528,7 +528,7 @@ size_t solve_ctx_bytes(int64_t n, int m, int maxiters, gnp_precision prec, int a
     const int64_t nb_cgs = (n + cgs_rpb(n) - 1) / cgs_rpb(n);
     const int64_t npartial = std::max<int64_t>(nb_cgs * (mp + 1), 2048);
     size_t b = kb * (size_t)n * (mp + m + 2) + sizeof(double) * n;
-    if (act_d > 0) b += 2 * sizeof(double) * (size_t)n * act_d;
+    if (act_d > 0) b += 2 * kb * (size_t)n * act_d;
     b += sizeof(double) * (4 + 2 * (m + 1) * m + 3 * m + 3 * (m + 1) + cap + 1 + npartial);
     b += sizeof(Ctl);
     return b;
@@ -556,8 +556,9 @@ gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
     GNP_HIP(hipMalloc(&c->vcur, kb * (size_t)n));
     GNP_HIP(hipMalloc(&c->w, kb * (size_t)n));
     GNP_HIP(hipMalloc(&c->r, sizeof(double) * n));
+    // activations: float64 / float32 elements (bfloat16 uses half of a float32 buffer)
     if (act_d > 0)
-        for (int i = 0; i < 2; ++i) GNP_HIP(hipMalloc(&c->act[i], sizeof(double) * n * act_d));
+        for (int i = 0; i < 2; ++i) GNP_HIP(hipMalloc(&c->act[i], kb * (size_t)n * act_d));
     GNP_HIP(hipMalloc(&c->tau, sizeof(double) * 4));
     GNP_HIP(hipMalloc(&c->H, sizeof(double) * (m + 1) * m));
     GNP_HIP(hipMalloc(&c->H0, sizeof(double) * (m + 1) * m));
