@@ -140,6 +140,17 @@ GNP_API gnp_status gnp_params_set_device(gnp_model *model, const double *buf_dev
 GNP_API gnp_status gnp_apply(gnp_model *model, const void *v_dev, void *z_dev, int nrhs,
                              gnp_precision prec, void *hip_stream);
 
+/* gnp_apply that also keeps every activation of the network: acts_dev holds
+ * (L+1) blocks of n * nrhs * d activations in the precision's storage type
+ * (float64, float32, or bfloat16 bit patterns as uint16 for GNP_BF16), node-
+ * major [n][nrhs][d]; block 0 = the encoder output X_0, block l = the output
+ * X_l of Res-GCONV layer l (Eq. (5)).  z_dev receives M(v) exactly as from
+ * gnp_apply (same kernels; the last layer additionally runs once without the
+ * fused decoder to store X_L).  For per-layer precision studies. */
+GNP_API gnp_status gnp_apply_layers(gnp_model *model, const void *v_dev, void *z_dev,
+                                    void *acts_dev, int nrhs, gnp_precision prec,
+                                    void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* FGMRES(m) with the network as right preconditioner (Algorithm 1)         */
 /* ------------------------------------------------------------------------ */

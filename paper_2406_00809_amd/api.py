@@ -146,6 +146,21 @@ class Model:
                                     _stream(stream)))
         return z
 
+    def apply_layers(self, v: torch.Tensor, prec="f32", stream=None):
+        """(z, acts): z = M(v) as from apply, and every activation of the
+        network, acts[l] = X_l of shape [n, nrhs, d] (l = 0: encoder output),
+        in the precision's storage type (bfloat16 for "bf16")."""
+        p = PREC[prec]
+        dt = KDTYPE[p]
+        nrhs = 1 if v.dim() == 1 else v.shape[1]
+        z = torch.empty_like(v)
+        sdt = {GNP_F64: torch.float64, GNP_F32: torch.float32, GNP_BF16: torch.bfloat16}[p]
+        acts = torch.empty((self.L + 1, self.system.n, nrhs, self.d), dtype=sdt, device=v.device)
+        check(_lib.load().gnp_apply_layers(self._h, _dev_ptr(v, dt, self.system.n * nrhs, "v"),
+                                           _dev_ptr(z, dt, self.system.n * nrhs, "z"),
+                                           C.c_void_p(acts.data_ptr()), nrhs, p, _stream(stream)))
+        return z, acts
+
     def train(self, steps: int, batch: int, lr: float = 1e-3, seed: int = 2, prec="f32",
               x_fixed: torch.Tensor | None = None, betas=(0.9, 0.999), eps: float = 1e-8,
               stream=None):

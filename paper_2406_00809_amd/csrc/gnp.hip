@@ -150,10 +150,13 @@ gnp_status model_workspace(gnp_model *m, int nrhs) {
 // ---------------------------------------------------------------------------
 // forward launch sequence
 // ---------------------------------------------------------------------------
+// layers (optional): (L+1) blocks of rows*D activations; when given, X_0 and
+// every layer output X_l go to block l (the last layer then runs once more
+// without the decoder to materialise X_L).
 template <typename G, typename IN, typename ZT, int D, int H>
 static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const double *tau,
                           G *act0, G *act1, const typename Act<G>::acc *vec, const void *wmat,
-                          const int *skip, hipStream_t st) {
+                          const int *skip, hipStream_t st, G *layers = nullptr) {
     gnp_system *s = m->sys;
     const int64_t rows = s->n * (int64_t)nrhs;
     const int grid = grid_for(rows, 64);
@@ -186,17 +189,21 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
         else return m->pk_bf16 + w0 + l * wstride;
     };
     (void)wmat;
-    hipLaunchKernelGGL((k_encoder<G, IN, D, H>), dim3(grid), dim3(BLOCK), 0, st, rows, nrhs, v,
-                       tau, vec, po.W1, po.c1, po.c2, w2, act0, skip);
     G *bufs[2] = {act0, act1};
+    auto buf = [&](int l) -> G * {  // holds X_l
+        return layers ? layers + (int64_t)l * rows * D : bufs[l % 2];
+    };
+    hipLaunchKernelGGL((k_encoder<G, IN, D, H>), dim3(grid), dim3(BLOCK), 0, st, rows, nrhs, v,
+                       tau, vec, po.W1, po.c1, po.c2, w2, buf(0), skip);
     for (int l = 0; l < m->L; ++l) {
-        const G *X = bufs[l % 2];
-        if (l < m->L - 1) {
+        const G *X = buf(l);
+        if (l < m->L - 1 || layers) {
             hipLaunchKernelGGL((k_layer<G, D, H, false, ZT>),
                                dim3(layer_grid<G, D, H, false, ZT>(rows)), dim3(BLOCK), 0, st, rows,
-                               nrhs, s->rp, s->ci, ahat, X, bufs[(l + 1) % 2], wcat(l), w3, vec,
+                               nrhs, s->rp, s->ci, ahat, X, buf(l + 1), wcat(l), w3, vec,
                                po.c3, po.W4, po.c4, tau, z, skip);
-        } else {
+        }
+        if (l == m->L - 1) {
             hipLaunchKernelGGL((k_layer<G, D, H, true, ZT>),
                                dim3(layer_grid<G, D, H, true, ZT>(rows)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, (G *)nullptr, wcat(l), w3, vec, po.c3,
@@ -208,30 +215,30 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
 template <int D, int H>
 static void forward_dispatch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                              const double *tau, void *a0, void *a1, const int *skip,
-                             hipStream_t st) {
+                             hipStream_t st, void *layers) {
     if (prec == GNP_F64)
         forward_typed<double, double, double, D, H>(m, (const double *)v, (double *)z, nrhs, tau,
                                                     (double *)a0, (double *)a1, m->theta64,
-                                                    nullptr, skip, st);
+                                                    nullptr, skip, st, (double *)layers);
     else if (prec == GNP_F32)
         forward_typed<float, float, float, D, H>(m, (const float *)v, (float *)z, nrhs, tau,
                                                  (float *)a0, (float *)a1, m->theta32, nullptr,
-                                                 skip, st);
+                                                 skip, st, (float *)layers);
     else
         forward_typed<uint16_t, float, float, D, H>(m, (const float *)v, (float *)z, nrhs, tau,
                                                     (uint16_t *)a0, (uint16_t *)a1, m->theta32,
-                                                    nullptr, skip, st);
+                                                    nullptr, skip, st, (uint16_t *)layers);
 }
 
 gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                           const double *tau, void *act0, void *act1, const int *skip,
-                          hipStream_t st) {
+                          hipStream_t st, void *layers) {
     if (m->sys->n * (int64_t)nrhs * m->d >= (int64_t)1 << 31)
         return fail(GNP_EINVAL, "n * nrhs * d must stay below 2^31 (32-bit gather offsets)");
     if (m->d == 16)
-        forward_dispatch<16, 32>(m, prec, v, z, nrhs, tau, act0, act1, skip, st);
+        forward_dispatch<16, 32>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers);
     else
-        forward_dispatch<32, 64>(m, prec, v, z, nrhs, tau, act0, act1, skip, st);
+        forward_dispatch<32, 64>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers);
     GNP_HIP(hipGetLastError());
     return GNP_OK;
 }
@@ -406,6 +413,24 @@ gnp_status gnp_apply(gnp_model *m, const void *v_dev, void *z_dev, int nrhs, gnp
         launch_colnorm<float>(m, (const float *)v_dev, nrhs, w.tau, w.partial, w.counter, nullptr,
                               st);
     return forward_launch(m, prec, v_dev, z_dev, nrhs, w.tau, w.act[0], w.act[1], nullptr, st);
+}
+
+gnp_status gnp_apply_layers(gnp_model *m, const void *v_dev, void *z_dev, void *acts_dev,
+                            int nrhs, gnp_precision prec, void *hip_stream) {
+    if (!m || !v_dev || !z_dev || !acts_dev) return fail(GNP_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > BLOCK) return fail(GNP_EINVAL, "nrhs must be in [1, 256]");
+    if (!valid_precision(prec)) return fail(GNP_EINVAL, "bad precision");
+    hipStream_t st = (hipStream_t)hip_stream;
+    GNP_TRY(model_workspace(m, nrhs));
+    ApplyWorkspace &w = m->ws;
+    if (prec == GNP_F64)
+        launch_colnorm<double>(m, (const double *)v_dev, nrhs, w.tau, w.partial, w.counter,
+                               nullptr, st);
+    else
+        launch_colnorm<float>(m, (const float *)v_dev, nrhs, w.tau, w.partial, w.counter, nullptr,
+                              st);
+    return forward_launch(m, prec, v_dev, z_dev, nrhs, w.tau, w.act[0], w.act[1], nullptr, st,
+                          acts_dev);
 }
 
 }  // extern "C"

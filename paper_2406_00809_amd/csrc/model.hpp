@@ -96,10 +96,11 @@ void launch_colnorm(gnp_model *m, const IN *v, int nrhs, double *tau_out, double
                     unsigned *counter, const int *skip, hipStream_t st);
 
 // z = M(v) given precomputed tau triples.  act0/act1: activation buffers.
-// When acts_out != nullptr, layer inputs X_0..X_{L-1} are written to
-// acts_out + l * n * nrhs * d (training forward) instead of ping-ponging.
+// When layers != nullptr, X_0 (encoder output) and every layer output X_l
+// are kept in block l of layers ((L+1) blocks of n * nrhs * d activations)
+// instead of ping-ponging between act0 and act1.
 gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                           const double *tau, void *act0, void *act1, const int *skip,
-                          hipStream_t st);
+                          hipStream_t st, void *layers = nullptr);
 
 }  // namespace gnp
