@@ -153,10 +153,14 @@ gnp_status model_workspace(gnp_model *m, int nrhs) {
 // layers (optional): (L+1) blocks of rows*D activations; when given, X_0 and
 // every layer output X_l go to block l (the last layer then runs once more
 // without the decoder to materialise X_L).
+// tau_partial (optional, one right-hand side, MFMA paths): per-block sums of
+// squares of v; the encoder then forms the tau triple itself and stores it
+// in tau.
 template <typename G, typename IN, typename ZT, int D, int H>
 static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const double *tau,
                           G *act0, G *act1, const typename Act<G>::acc *vec, const void *wmat,
-                          const int *skip, hipStream_t st, G *layers = nullptr) {
+                          const int *skip, hipStream_t st, G *layers = nullptr,
+                          const double *tau_partial = nullptr, int tau_nblk = 0) {
     gnp_system *s = m->sys;
     const int64_t rows = s->n * (int64_t)nrhs;
     const int grid = grid_for(rows, 64);
@@ -177,7 +181,7 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
         w0 = m->pf.Wcat0;
         wstride = m->pf.Wcat_stride;
     } else {
-        ahat = (const typename Act<G>::vt *)s->ahat32;
+        ahat = (const typename Act<G>::vt *)s->ahat16;
         w2 = m->pk_bf16 + m->pb.W2;
         w3 = m->pk_bf16 + m->pb.W3;
         w0 = m->pb.Wcat0;
@@ -193,18 +197,25 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
     auto buf = [&](int l) -> G * {  // holds X_l
         return layers ? layers + (int64_t)l * rows * D : bufs[l % 2];
     };
-    hipLaunchKernelGGL((k_encoder<G, IN, D, H>), dim3(grid), dim3(BLOCK), 0, st, rows, nrhs, v,
-                       tau, vec, po.W1, po.c1, po.c2, w2, buf(0), skip);
+    if constexpr (sizeof(G) == 8) {
+        hipLaunchKernelGGL((k_encoder<G, IN, D, H>), dim3(grid), dim3(BLOCK), 0, st, rows, nrhs,
+                           v, tau, vec, po.W1, po.c1, po.c2, w2, buf(0), skip);
+    } else {
+        const int ge = std::min(grid, resident_blocks<k_encoder_p<G, IN, D, H>>());
+        hipLaunchKernelGGL((k_encoder_p<G, IN, D, H>), dim3(ge), dim3(BLOCK), 0, st, rows, nrhs,
+                           v, const_cast<double *>(tau), vec, po.W1, po.c1, po.c2, w2, buf(0),
+                           skip, tau_partial, tau_nblk, s->n);
+    }
     for (int l = 0; l < m->L; ++l) {
         const G *X = buf(l);
         if (l < m->L - 1 || layers) {
-            hipLaunchKernelGGL((k_layer<G, D, H, false, ZT>),
+            hipLaunchKernelGGL((layer_kernel<G, D, H, false, ZT>()),
                                dim3(layer_grid<G, D, H, false, ZT>(rows)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, buf(l + 1), wcat(l), w3, vec,
                                po.c3, po.W4, po.c4, tau, z, skip);
         }
         if (l == m->L - 1) {
-            hipLaunchKernelGGL((k_layer<G, D, H, true, ZT>),
+            hipLaunchKernelGGL((layer_kernel<G, D, H, true, ZT>()),
                                dim3(layer_grid<G, D, H, true, ZT>(rows)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, (G *)nullptr, wcat(l), w3, vec, po.c3,
                                po.W4, po.c4, tau, z, skip);
@@ -215,7 +226,8 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
 template <int D, int H>
 static void forward_dispatch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                              const double *tau, void *a0, void *a1, const int *skip,
-                             hipStream_t st, void *layers) {
+                             hipStream_t st, void *layers, const double *tau_partial,
+                             int tau_nblk) {
     if (prec == GNP_F64)
         forward_typed<double, double, double, D, H>(m, (const double *)v, (double *)z, nrhs, tau,
                                                     (double *)a0, (double *)a1, m->theta64,
@@ -223,22 +235,32 @@ static void forward_dispatch(gnp_model *m, gnp_precision prec, const void *v, vo
     else if (prec == GNP_F32)
         forward_typed<float, float, float, D, H>(m, (const float *)v, (float *)z, nrhs, tau,
                                                  (float *)a0, (float *)a1, m->theta32, nullptr,
-                                                 skip, st, (float *)layers);
+                                                 skip, st, (float *)layers, tau_partial,
+                                                 tau_nblk);
     else
         forward_typed<uint16_t, float, float, D, H>(m, (const float *)v, (float *)z, nrhs, tau,
                                                     (uint16_t *)a0, (uint16_t *)a1, m->theta32,
-                                                    nullptr, skip, st, (uint16_t *)layers);
+                                                    nullptr, skip, st, (uint16_t *)layers,
+                                                    tau_partial, tau_nblk);
 }
 
 gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                           const double *tau, void *act0, void *act1, const int *skip,
-                          hipStream_t st, void *layers) {
-    if (m->sys->n * (int64_t)nrhs * m->d >= (int64_t)1 << 31)
-        return fail(GNP_EINVAL, "n * nrhs * d must stay below 2^31 (32-bit gather offsets)");
+                          hipStream_t st, void *layers, const double *tau_partial,
+                          int tau_nblk) {
+    if (tau_partial && (nrhs != 1 || prec == GNP_F64))
+        return fail(GNP_EINVAL, "the encoder forms tau only for one float32/bfloat16 rhs");
+    const int64_t elem = prec == GNP_F64 ? 8 : (prec == GNP_F32 ? 4 : 2);
+    if (m->sys->n * (int64_t)nrhs * m->d * elem >= (int64_t)1 << 32)
+        return fail(GNP_EINVAL,
+                    "an activation block (n * nrhs * d elements) must stay below 4 GiB "
+                    "(32-bit gather offsets)");
     if (m->d == 16)
-        forward_dispatch<16, 32>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers);
+        forward_dispatch<16, 32>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers,
+                                 tau_partial, tau_nblk);
     else
-        forward_dispatch<32, 64>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers);
+        forward_dispatch<32, 64>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers,
+                                 tau_partial, tau_nblk);
     GNP_HIP(hipGetLastError());
     return GNP_OK;
 }
@@ -263,10 +285,10 @@ static void layer_once(gnp_model *m, int nrhs, int l, hipStream_t st) {
         vec = (const typename Act<G>::acc *)m->theta32;
     } else {
         wc = m->pk_bf16 + m->pb.Wcat0 + l * m->pb.Wcat_stride;
-        ahat = (const typename Act<G>::vt *)s->ahat32;
+        ahat = (const typename Act<G>::vt *)s->ahat16;
         vec = (const typename Act<G>::acc *)m->theta32;
     }
-    hipLaunchKernelGGL((k_layer<G, D, H, false, float>), dim3(grid), dim3(BLOCK), 0, st, rows,
+    hipLaunchKernelGGL((layer_kernel<G, D, H, false, float>()), dim3(grid), dim3(BLOCK), 0, st, rows,
                        nrhs, s->rp, s->ci, ahat, (const G *)m->ws.act[0], (G *)m->ws.act[1], wc,
                        (const void *)nullptr, vec, m->po.c3, m->po.W4, m->po.c4,
                        (const double *)m->ws.tau, (float *)nullptr, (const int *)nullptr);

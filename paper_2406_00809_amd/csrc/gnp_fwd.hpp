@@ -19,6 +19,8 @@
 // lane's four results are four consecutive features (4 (l/16) + j) of one row
 // (l % 16) and leave as a single 8- or 16-byte store.
 #pragma once
+#include <type_traits>
+
 #include "model.hpp"
 
 namespace gnp {
@@ -34,6 +36,7 @@ template <> struct Act<double> {
     using vt = double;   // A-hat value type
     static __device__ __forceinline__ double get(double v) { return v; }
     static __device__ __forceinline__ double put(double v) { return v; }
+    static __device__ __forceinline__ double wf(double a) { return a; }
 };
 template <> struct Act<float> {
     using acc = float;
@@ -41,13 +44,15 @@ template <> struct Act<float> {
     using vt = float;
     static __device__ __forceinline__ float get(float v) { return v; }
     static __device__ __forceinline__ float put(float v) { return v; }
+    static __device__ __forceinline__ float wf(float a) { return a; }
 };
 template <> struct Act<uint16_t> {
     using acc = float;
     using mt = uint16_t;
-    using vt = float;
+    using vt = uint16_t;  // A-hat stored in bfloat16 as well
     static __device__ __forceinline__ float get(uint16_t v) { return bf2f(v); }
     static __device__ __forceinline__ uint16_t put(float v) { return f2bf(v); }
+    static __device__ __forceinline__ float wf(uint16_t a) { return bf2f(a); }
 };
 
 template <typename G, int N>
@@ -185,6 +190,117 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
 }
 
 // ---------------------------------------------------------------------------
+// Persistent encoder for the MFMA paths (float32 / bfloat16 activations):
+// the weights a lane needs are loaded once, and the input of the next tile
+// is requested before the current one is computed.  With tau_partial (a
+// single right-hand side), every block first forms the tau triple of Eq. (6)
+// itself from the per-block sums of squares of v (the same fixed-order sum
+// in every block) and block 0 publishes it for the decoder.
+// ---------------------------------------------------------------------------
+template <typename G, typename IN, int D, int H>
+__global__ __launch_bounds__(BLOCK) void k_encoder_p(
+    int64_t rows, int B, const IN *__restrict__ v, double *__restrict__ tau,
+    const float *__restrict__ vec, int64_t oW1, int64_t oc1, int64_t oc2,
+    const void *__restrict__ w2, G *__restrict__ E, const int *__restrict__ skip,
+    const double *__restrict__ tau_partial, int tau_nblk, int64_t n) {
+    static_assert(sizeof(G) <= 4, "MFMA encoder");
+    if (skip && *skip) return;
+    __shared__ double sh[BLOCK / WAVE];
+    const int lane = threadIdx.x % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    double tau1 = 0.0;  // sqrt(n) / tau when the triple is formed here
+    if (tau_partial) {
+        const double tv = sqrt(sum_partials(tau_nblk, tau_partial, 1, sh));
+        const double sqn = sqrt((double)n);
+        tau1 = tv > 0.0 ? sqn / tv : 0.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            tau[0] = tv;
+            tau[1] = tau1;
+            tau[2] = tv / sqn;
+        }
+    }
+    const float *W1 = vec + oW1, *c1 = vec + oc1, *c2 = vec + oc2;
+    // hidden-unit weights in the layout of the MFMA B operand, output bias in
+    // the result layout, W2 fragments as the A operand
+    constexpr int KG = sizeof(G) == 2 ? H / 32 : H / 4;  // k groups
+    constexpr int KE = sizeof(G) == 2 ? 8 : 1;           // k per group per lane
+    float w1r[KG][KE], c1r[KG][KE], c2r[D / 16][4];
+#pragma unroll
+    for (int g = 0; g < KG; ++g)
+#pragma unroll
+        for (int i = 0; i < KE; ++i) {
+            const int k = sizeof(G) == 2 ? g * 32 + 8 * (lane / 16) + i : g * 4 + lane / 16;
+            w1r[g][i] = W1[k];
+            c1r[g][i] = c1[k];
+        }
+#pragma unroll
+    for (int nt = 0; nt < D / 16; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c2r[nt][j] = c2[nt * 16 + 4 * (lane / 16) + j];
+    using Frag = typename std::conditional<sizeof(G) == 2, bf16x8, float>::type;
+    Frag pk[KG][D / 16];
+#pragma unroll
+    for (int g = 0; g < KG; ++g)
+#pragma unroll
+        for (int nt = 0; nt < D / 16; ++nt) {
+            if constexpr (sizeof(G) == 2)
+                pk[g][nt] = load_bf16x8((const uint16_t *)w2 +
+                                        ((int64_t)(g * (D / 16) + nt) * 64 + lane) * 8);
+            else
+                pk[g][nt] = ((const float *)w2)[(g * (D / 16) + nt) * 64 + lane];
+        }
+    const int64_t ntiles = (rows + 15) / 16, nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
+    IN vn = v[t * 16 + lane % 16 < rows ? t * 16 + lane % 16 : rows - 1];
+    for (; t < ntiles; t += nw) {
+        const int64_t ra = t * 16 + lane % 16;
+        const IN vc = vn;
+        const int64_t rn = (t + nw) * 16 + lane % 16;
+        vn = v[rn < rows ? rn : rows - 1];  // next tile's input, clamped
+        const double ts = tau_partial ? tau1 : tau[3 * ((uint32_t)ra % (uint32_t)B) + 1];
+        const float u = ra < rows ? (float)(ts * (double)vc) : 0.f;
+        f32x4 o[D / 16];
+#pragma unroll
+        for (int nt = 0; nt < D / 16; ++nt) o[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+            if constexpr (sizeof(G) == 2) {
+                uint16_t av[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) av[i] = f2bf(fmaxf(u * w1r[g][i] + c1r[g][i], 0.f));
+                const bf16x8 hf = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+                for (int nt = 0; nt < D / 16; ++nt)
+                    o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pk[g][nt], hf, o[nt], 0, 0, 0);
+            } else {
+                const float a = fmaxf(u * w1r[g][0] + c1r[g][0], 0.f);
+#pragma unroll
+                for (int nt = 0; nt < D / 16; ++nt)
+                    o[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(pk[g][nt], a, o[nt], 0, 0, 0);
+            }
+        }
+        if (ra < rows) {
+#pragma unroll
+            for (int nt = 0; nt < D / 16; ++nt)
+                store4<G>(E + ra * D + nt * 16 + 4 * (lane / 16), o[nt][0] + c2r[nt][0],
+                          o[nt][1] + c2r[nt][1], o[nt][2] + c2r[nt][2], o[nt][3] + c2r[nt][3]);
+        }
+    }
+}
+
+// Blocks of a kernel that fit on the device at once (occupancy x CUs).
+template <auto K> inline int resident_blocks() {
+    static const int resident = [] {  // initialised once, thread-safe
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K, BLOCK, 0);
+        return (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+    }();
+    return resident;
+}
+
+// ---------------------------------------------------------------------------
 // Res-GCONV layer (Eq. (5)), fused:  T = A-hat X (CSR gather, 4 lanes per
 // row, d/4 features per lane) -> LDS tile [X | T] -> [X | T] [U; W] on MFMA
 // -> ReLU -> store.  With DEC the output tile stays in LDS and feeds the
@@ -199,7 +315,7 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
 // Gather offsets are 32-bit (the launchers check rows * d < 2^31).
 // ---------------------------------------------------------------------------
 template <typename G, int D, int H, bool DEC, typename ZT>
-__global__ __launch_bounds__(BLOCK) void k_layer(
+__device__ __forceinline__ void layer_tiles(
     int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const typename Act<G>::vt *__restrict__ ahat, const G *__restrict__ X, G *__restrict__ Y,
     const void *__restrict__ wcat, const void *__restrict__ w3,
@@ -213,11 +329,15 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
     constexpr int CAP = 256, NC = CAP / WAVE;
     __shared__ __attribute__((aligned(16))) mt As[BLOCK / WAVE][16][LD];
     __shared__ int32_t sRp[BLOCK / WAVE][17];
-    __shared__ int32_t sCi[BLOCK / WAVE][CAP];
+    __shared__ uint32_t sCo[BLOCK / WAVE][CAP];  // byte offset of row (column, rhs 0) in X
     __shared__ vt_t sVa[BLOCK / WAVE][CAP];
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    // the wavefront index is uniform: keep it (and the whole tile walk, the
+    // rowptr slice and the CSR slice bounds) in scalar registers
+    const int lane = threadIdx.x % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv);
     const int64_t ntiles = walk.end, nw = walk.stride;
+    const uint32_t rowbytes = (uint32_t)B * (uint32_t)(D * sizeof(G));
 
     auto node_range = [&](int64_t t, int64_t &ifirst, int &nn) {
         const int64_t r0 = t * 16;
@@ -236,8 +356,8 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
         int64_t ifirst;
         int nn;
         node_range(t, ifirst, nn);
-        kbeg = __shfl(rpv, 0, WAVE);
-        cnt = __shfl(rpv, nn, WAVE) - kbeg;
+        kbeg = __builtin_amdgcn_readfirstlane(rpv);
+        cnt = __builtin_amdgcn_readlane(rpv, nn) - kbeg;
         if (cnt > 0 && cnt <= CAP) {  // cnt = 0: empty rows, nothing to load
 #pragma unroll
             for (int u = 0; u < NC; ++u) {
@@ -270,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
             for (int u = 0; u < NC; ++u) {
                 const int idx = lane + WAVE * u;
                 if (idx < cnt) {
-                    sCi[wv][idx] = cv[u];
+                    sCo[wv][idx] = (uint32_t)cv[u] * rowbytes;
                     sVa[wv][idx] = av[u];
                 }
             }
@@ -295,33 +415,54 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
                 load_feats<G, D / 4>(X + r * D + q * (D / 4), sv);
                 if (staged) {
                     // neighbours in batches of NB, kept packed until the FMAs;
-                    // short rows re-load a valid neighbour with weight 0
+                    // short rows re-load a valid neighbour with weight 0.
+                    // Byte offsets from the uniform base (the launchers keep
+                    // the activation block below 4 GiB).
                     constexpr int NB = sizeof(G) == 2 ? 8 : 4;
                     constexpr int CB = (D / 4) * (int)sizeof(G);
+                    const uint32_t lane_off =
+                        ((uint32_t)b * D + (uint32_t)(q * (D / 4))) * (uint32_t)sizeof(G);
+                    const char *Xb = reinterpret_cast<const char *>(X);
                     for (int32_t k0 = ks; k0 < ke; k0 += NB) {
                         Chunk<CB> raw[NB];
-                        acc_t wgt[NB];
+                        vt_t wgt[NB];
 #pragma unroll
                         for (int u = 0; u < NB; ++u) {
                             const bool ok = k0 + u < ke;
                             const int32_t kk = ok ? k0 + u : ks;
-                            const uint32_t c = (uint32_t)sCi[wv][kk];
-                            wgt[u] = ok ? (acc_t)sVa[wv][kk] : (acc_t)0;
-                            const uint32_t off = (c * (uint32_t)B + (uint32_t)b) * (uint32_t)D +
-                                                 (uint32_t)(q * (D / 4));
-                            raw[u] = *reinterpret_cast<const Chunk<CB> *>(X + off);
+                            wgt[u] = ok ? sVa[wv][kk] : (vt_t)0;
+                            raw[u] = *reinterpret_cast<const Chunk<CB> *>(Xb + sCo[wv][kk] +
+                                                                          lane_off);
                         }
+                        if constexpr (sizeof(G) == 2) {
+                            // bf16 pairs times packed weights (a, 0) and (0, a):
+                            // one v_dot2 per element, no unpacking
 #pragma unroll
-                        for (int u = 0; u < NB; ++u) {
-                            const G *e8 = reinterpret_cast<const G *>(&raw[u]);
+                            for (int u = 0; u < NB; ++u) {
+                                const uint32_t wlo = (uint32_t)wgt[u], whi = wlo << 16;
 #pragma unroll
-                            for (int e = 0; e < D / 4; ++e) ta[e] += wgt[u] * Act<G>::get(e8[e]);
+                                for (int j = 0; j < CB / 4; ++j) {
+                                    const bf16x2 xv = __builtin_bit_cast(bf16x2, raw[u].w[j]);
+                                    ta[2 * j] = __builtin_amdgcn_fdot2_f32_bf16(
+                                        xv, __builtin_bit_cast(bf16x2, wlo), ta[2 * j], false);
+                                    ta[2 * j + 1] = __builtin_amdgcn_fdot2_f32_bf16(
+                                        xv, __builtin_bit_cast(bf16x2, whi), ta[2 * j + 1], false);
+                                }
+                            }
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < NB; ++u) {
+                                const G *e8 = reinterpret_cast<const G *>(&raw[u]);
+#pragma unroll
+                                for (int e = 0; e < D / 4; ++e)
+                                    ta[e] += Act<G>::wf(wgt[u]) * Act<G>::get(e8[e]);
+                            }
                         }
                     }
                 } else {
                     for (int32_t k = kbeg + ks; k < kbeg + ke; ++k) {
                         const uint32_t c = (uint32_t)ci[k];
-                        const acc_t a = (acc_t)ahat[k];
+                        const acc_t a = Act<G>::wf(ahat[k]);
                         acc_t xv[D / 4];
                         load_feats<G, D / 4>(
                             X + (c * (uint32_t)B + (uint32_t)b) * (uint32_t)D + q * (D / 4), xv);
@@ -480,6 +621,37 @@ __global__ __launch_bounds__(BLOCK) void k_layer(
     }
 }
 
+#define GNP_LAYER_PARAMS                                                                       \
+    int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,       \
+        const typename Act<G>::vt *__restrict__ ahat, const G *__restrict__ X,                 \
+        G *__restrict__ Y, const void *__restrict__ wcat, const void *__restrict__ w3,         \
+        const typename Act<G>::acc *__restrict__ vec, int64_t oc3, int64_t oW4, int64_t oc4,   \
+        const double *__restrict__ tau, ZT *__restrict__ z, const int *__restrict__ skip
+#define GNP_LAYER_ARGS rows, B, rp, ci, ahat, X, Y, wcat, w3, vec, oc3, oW4, oc4, tau, z, skip
+
+template <typename G, int D, int H, bool DEC, typename ZT>
+__global__ __launch_bounds__(BLOCK) void k_layer(GNP_LAYER_PARAMS) {
+    layer_tiles<G, D, H, DEC, ZT>(GNP_LAYER_ARGS);
+}
+
+// The same kernel held to 128 registers (4 wavefronts per SIMD): more
+// wavefronts in flight hide more of the gather latency.  Used for the
+// float32 and bfloat16 layers without the fused decoder, which fit without
+// spilling.
+template <typename G, int D, int H, typename ZT>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_layer_w4(
+    GNP_LAYER_PARAMS) {
+    layer_tiles<G, D, H, false, ZT>(GNP_LAYER_ARGS);
+}
+#undef GNP_LAYER_PARAMS
+#undef GNP_LAYER_ARGS
+
+// The layer kernel to launch for a configuration.
+template <typename G, int D, int H, bool DEC, typename ZT> inline auto layer_kernel() {
+    if constexpr (!DEC && sizeof(G) < 8) return &k_layer_w4<G, D, H, ZT>;
+    else return &k_layer<G, D, H, DEC, ZT>;
+}
+
 // Grid of the persistent layer kernel: as many blocks as can be resident at
 // once (occupancy x compute units), at most one 64-row block per tile group.
 template <typename G, int D, int H, bool DEC, typename ZT>
@@ -488,8 +660,8 @@ inline int layer_grid(int64_t rows) {
         int dev = 0, cus = 0, per_cu = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_layer<G, D, H, DEC, ZT>,
-                                                           BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, layer_kernel<G, D, H, DEC, ZT>(), BLOCK, 0);
         return (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
     }();
     const int64_t need = (rows + 63) / 64;

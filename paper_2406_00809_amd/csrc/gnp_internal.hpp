@@ -16,6 +16,7 @@ namespace gnp {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
@@ -75,6 +76,26 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
 // every block writes its partials, then calls this; exactly one block (the
 // last to arrive) gets true and may read all partials, which it sums in
 // block order.  The ticket counter is reset by that block.
+// Sum of partial[k * stride] over k < nblk in one fixed order (every thread
+// of the block takes part and receives the sum): any block that calls it on
+// the same data gets the same bits.  scratch: >= BLOCK / WAVE doubles.
+__device__ __forceinline__ double sum_partials(int nblk, const double *__restrict__ partial,
+                                               int stride, double *scratch) {
+    const int t = threadIdx.x;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int blk0 = t; blk0 < nblk; blk0 += 4 * BLOCK) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {  // clamped, unconditional loads
+            const int blk = blk0 + u * BLOCK;
+            v[u] = partial[(int64_t)(blk < nblk ? blk : nblk - 1) * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] += (blk0 + u * BLOCK < nblk) ? v[u] : 0.0;
+    }
+    return block_sum((a[0] + a[1]) + (a[2] + a[3]), scratch);
+}
+
 __device__ __forceinline__ bool last_block(unsigned *counter) {
     __shared__ int is_last;
     __threadfence();
@@ -146,6 +167,7 @@ struct gnp_system {
     float *val32 = nullptr;                      // system A, float32
     double *ahat64 = nullptr;                    // A-hat = A / gamma
     float *ahat32 = nullptr;
+    uint16_t *ahat16 = nullptr;                  // A-hat in bfloat16 (the BF16 network)
     int32_t *trp = nullptr, *tci = nullptr;      // CSR of A^T
     double *tval64 = nullptr;                    // A^T
     float *tval32 = nullptr;

@@ -42,19 +42,7 @@ __device__ void reduce_columns(int nblk, int ncol, const double *__restrict__ pa
     __shared__ double sh[BLOCK];
     const int t = threadIdx.x;
     if (ncol == 1) {
-        // every thread takes blocks t, t + BLOCK, ... (independent loads)
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int blk0 = t; blk0 < nblk; blk0 += 4 * BLOCK) {
-            double v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int blk = blk0 + u * BLOCK;
-                v[u] = partial[(int64_t)(blk < nblk ? blk : nblk - 1) * stride];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] += (blk0 + u * BLOCK < nblk) ? v[u] : 0.0;
-        }
-        const double s = block_sum((a[0] + a[1]) + (a[2] + a[3]), sh);
+        const double s = sum_partials(nblk, partial, stride, sh);
         if (t == 0) out[0] = s;
         __syncthreads();
         return;
@@ -592,14 +580,21 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     const int gcgs = (int)((n + rpb - 1) / rpb);
     const int pstride = MP + 1;
     const int *skip = &c->ctl->cycle_done;
+    // tau of the network input: formed by the encoder from the normalisation
+    // partials (float32/bfloat16 networks) or by its own kernel (float64);
+    // not needed without a network
+    const bool tau_in_encoder = model && c->prec != GNP_F64;
+    const bool tau_kernel = model && !tau_in_encoder;
     hipLaunchKernelGGL((k_normalize<KT, double, MP>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, V, 0,
                        vcur, c->partial, c->ctl, 1);
-    hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau, c->ctl);
+    if (tau_kernel)
+        hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
+                           c->ctl);
     for (int j = 0; j < nsteps; ++j) {
         KT *zj = model ? Z + (int64_t)j * n : vcur;
         if (model)
             GNP_TRY(forward_launch(model, c->prec, vcur, zj, 1, c->tau, c->act[0], c->act[1], skip,
-                                   st));
+                                   st, nullptr, tau_in_encoder ? c->partial : nullptr, sg));
         spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
                            (const KT *)V, j, w, (const double *)nullptr, c->partial, pstride,
@@ -620,8 +615,9 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                            c->hist);
         hipLaunchKernelGGL((k_normalize<KT, KT, MP>), dim3(sg), dim3(BLOCK), 0, st, n,
                            (const KT *)w, V, j + 1, vcur, c->partial, c->ctl, 0);
-        hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
-                           c->ctl);
+        if (tau_kernel)
+            hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
+                               c->ctl);
     }
     hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(BLOCK), 0, st, c->ctl, c->H, c->g, c->y);
     if (model)

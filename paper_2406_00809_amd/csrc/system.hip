@@ -174,11 +174,16 @@ __global__ void k_gather(int64_t nnz, const int32_t *__restrict__ perm,
     }
 }
 
+__global__ void k_to_bf16(int64_t count, const float *__restrict__ src, uint16_t *__restrict__ dst) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) dst[k] = __builtin_bit_cast(uint16_t, (__bf16)src[k]);  // round to nearest even
+}
+
 static void sys_free(gnp_system *s) {
     if (!s) return;
     void *ptrs[] = {s->rp,     s->ci,      s->val64,  s->val32,   s->ahat64,  s->ahat32,
                     s->trp,    s->tci,     s->tval64, s->tval32,  s->tahat64, s->tahat32,
-                    s->counters, s->scratch};
+                    s->ahat16,   s->counters, s->scratch};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     solve_cache_free(s->solve_cache);
@@ -267,6 +272,7 @@ gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr, cons
         GNP_TRY(dalloc(&s->val32, nnz));
         GNP_TRY(dalloc(&s->ahat64, nnz));
         GNP_TRY(dalloc(&s->ahat32, nnz));
+        GNP_TRY(dalloc(&s->ahat16, nnz));
         GNP_TRY(dalloc(&s->trp, n + 1));
         GNP_TRY(dalloc(&s->tci, nnz));
         GNP_TRY(dalloc(&s->tval64, nnz));
@@ -314,6 +320,8 @@ gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr, cons
         // A-hat = A / gamma and its transpose
         hipLaunchKernelGGL(k_div, dim3(gk), dim3(BLOCK), 0, st, nnz, s->val64, gam + 1, s->ahat64,
                            s->ahat32);
+        hipLaunchKernelGGL(k_to_bf16, dim3(gk), dim3(BLOCK), 0, st, nnz, (const float *)s->ahat32,
+                           s->ahat16);
         hipLaunchKernelGGL(k_gather, dim3(gk), dim3(BLOCK), 0, st, nnz, tperm, s->ahat64,
                            s->tahat64, s->tahat32);
         GNP_HIP(hipGetLastError());

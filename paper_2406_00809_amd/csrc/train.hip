@@ -497,8 +497,10 @@ static gnp_status train_ctx_get(gnp_model *m, gnp_precision prec, int nrhs, int 
     TrainCtx *c = (TrainCtx *)m->train_ctx;
     const size_t es = prec == GNP_F64 ? 8 : 4;
     const int64_t rows = m->sys->n * (int64_t)nrhs;
-    if (rows * m->d >= (int64_t)1 << 31)
-        return fail(GNP_EINVAL, "n * batch * d must stay below 2^31 (32-bit gather offsets)");
+    if (rows * m->d * (int64_t)es >= (int64_t)1 << 32)
+        return fail(GNP_EINVAL,
+                    "an activation block (n * batch * d elements) must stay below 4 GiB "
+                    "(32-bit gather offsets)");
     if (c && c->nrhs == nrhs && c->es == es && c->loss_cap >= steps) {
         c->prec = prec;
         *out = c;
@@ -572,7 +574,7 @@ static void fwd_save(gnp_model *m, TrainCtx *c, const T *bin, T *z, hipStream_t 
         const void *wc;
         if constexpr (sizeof(T) == 8) wc = m->theta64 + po.U0 + (int64_t)l * 2 * D * D;
         else wc = m->pk_f32 + m->pf.Wcat0 + l * m->pf.Wcat_stride;
-        hipLaunchKernelGGL((k_layer<T, D, H, false, T>), dim3(layer_grid<T, D, H, false, T>(rows)),
+        hipLaunchKernelGGL((layer_kernel<T, D, H, false, T>()), dim3(layer_grid<T, D, H, false, T>(rows)),
                            dim3(BLOCK), 0, st, rows, B,
                            s->rp, s->ci, ahat, acts + (int64_t)l * rows * D,
                            acts + (int64_t)(l + 1) * rows * D, wc, (const void *)nullptr, vec,
