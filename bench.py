@@ -344,7 +344,8 @@ def main():
     # ---- dominant kernel: one Res-GCONV layer, same launch configuration
     lay_ms = M.time_layer(nrhs=1, prec=args.prec, reps=200)
     s_act = {"bf16": 2, "f32": 4, "f64": 8}[args.prec]
-    s_val = 8 if args.prec == "f64" else 4
+    # A-hat values are stored in the network's precision (bfloat16 for bf16)
+    s_val = {"bf16": 2, "f32": 4, "f64": 8}[args.prec]
     layer_bytes = (s_val + 4) * S.nnz + 4 * (S.n + 1) + 2 * S.n * d * s_act
     achieved = layer_bytes / (lay_ms * 1e-3) / 1e9
     # SpMV (float32): 8 nnz + 4 (n+1) + 8 n bytes

@@ -636,8 +636,7 @@ __global__ __launch_bounds__(BLOCK) void k_layer(GNP_LAYER_PARAMS) {
 
 // The same kernel held to 128 registers (4 wavefronts per SIMD): more
 // wavefronts in flight hide more of the gather latency.  Used for the
-// float32 and bfloat16 layers without the fused decoder, which fit without
-// spilling.
+// bfloat16 layers without the fused decoder, which fit without spilling.
 template <typename G, int D, int H, typename ZT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_layer_w4(
     GNP_LAYER_PARAMS) {
@@ -648,7 +647,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
 
 // The layer kernel to launch for a configuration.
 template <typename G, int D, int H, bool DEC, typename ZT> inline auto layer_kernel() {
-    if constexpr (!DEC && sizeof(G) < 8) return &k_layer_w4<G, D, H, ZT>;
+    if constexpr (!DEC && sizeof(G) == 2) return &k_layer_w4<G, D, H, ZT>;
     else return &k_layer<G, D, H, DEC, ZT>;
 }
 
