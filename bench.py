@@ -341,6 +341,43 @@ def main():
                                       "iters": inf3["iters"],
                                       "rel_res_true": inf3["rel_res_true"]}
 
+        # 32 right-hand sides b ~ N(0, I): float32 network one solve at a time,
+        # against the bfloat16 network served with 32 concurrent slots
+        nb = 32
+        bs = [I.rhs_normal(S.n, 500 + k) for k in range(nb)]
+        t1 = time.perf_counter()
+        conv32 = 0
+        for bk in bs:
+            bd = torch.as_tensor(bk, dtype=torch.float64, device=dev)
+            _, inf4, _ = api.fgmres_solve(S, bd, M, m=m, rtol=1e-8, maxiters=args.maxiters,
+                                          prec="f32", want_hist=False)
+            conv32 += inf4["converged"]
+        torch.cuda.synchronize()
+        seq = nb / (time.perf_counter() - t1)
+        srv = api.Server(64 << 30, nb, m, args.maxiters, prec=args.prec)
+        sid = srv.register(S, M)
+        srv.submit(sid, bs[0], rtol=1e-8, maxiters=args.maxiters)  # warm the workspaces
+        srv.drain(600.0)
+        t1 = time.perf_counter()
+        tickets = [srv.submit(sid, bk, rtol=1e-8, maxiters=args.maxiters) for bk in bs]
+        srv.drain(600.0)
+        served = nb / (time.perf_counter() - t1)
+        convs, its = 0, []
+        for t in tickets:
+            _, inf5, _ = srv.poll(t, S.n)
+            convs += inf5["converged"]
+            its.append(inf5["iters"])
+        st = srv.stats()
+        srv.close()
+        extra["rhs32_fp32_single_solves_sequential"] = {"solves_per_s": seq, "converged": conv32}
+        extra["rhs32_served_concurrent"] = {"solves_per_s": served, "converged": convs,
+                                            "mean_iters": float(np.mean(its)),
+                                            "max_active": st["max_active"],
+                                            "latency_p50_ms": 1e3 * st["latency_p50_s"],
+                                            "latency_p99_ms": 1e3 * st["latency_p99_s"]}
+        log(f"32 rhs: float32 single solves {seq:.2f}/s ({conv32} converged), served "
+            f"{args.prec} {served:.2f}/s ({convs} converged)")
+
     # ---- dominant kernel: one Res-GCONV layer, same launch configuration
     lay_ms = M.time_layer(nrhs=1, prec=args.prec, reps=200)
     s_act = {"bf16": 2, "f32": 4, "f64": 8}[args.prec]
