@@ -647,8 +647,12 @@ static void launch_residual(SolveCtx *c, const double *b, const double *x, int i
     gnp_system *s = c->sys;
     const int64_t n = s->n;
     const double avg = (double)s->nnz / (double)n;
-    const int grid = grid_for(n, BLOCK / 8, 1024);
-    if (avg <= 8.0)
+    const int G = avg <= 12.0 ? 4 : (avg <= 24.0 ? 8 : 16);
+    const int grid = grid_for(n, BLOCK / G, 1024);
+    if (G == 4)
+        hipLaunchKernelGGL(k_residual<4>, dim3(grid), dim3(BLOCK), 0, st, n, s->rp, s->ci,
+                           s->val64, x, b, c->r, c->partial);
+    else if (G == 8)
         hipLaunchKernelGGL(k_residual<8>, dim3(grid), dim3(BLOCK), 0, st, n, s->rp, s->ci,
                            s->val64, x, b, c->r, c->partial);
     else
