@@ -188,6 +188,21 @@ GNP_API gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const double 
                                 void *hip_stream);
 
 
+/* Solve A x_k = b_k for nrhs right-hand sides at once (each one exactly as
+ * fgmres_solve would, step for step), with one network application per
+ * Arnoldi step for the whole batch (Sec. 2.2: one preconditioner serves every
+ * right-hand side of its system).  b_dev, x_dev: nrhs float64 vectors of
+ * length n, one after the other (b_k at b_dev + k n); x_dev holds the x0 on
+ * entry and the solutions on exit.  The right-hand sides run in lockstep
+ * restart cycles; one that has converged (or reached maxiters) idles while
+ * the others go on.  infos (host, nrhs entries, optional) receives each
+ * solve's gnp_solve_info.  model is required; prec is GNP_F32 or GNP_BF16.
+ * Errors: as fgmres_solve, plus GNP_EINVAL for nrhs outside [1, 256]. */
+GNP_API gnp_status fgmres_solve_batch(gnp_system *sys, gnp_model *model, const double *b_dev,
+                                      double *x_dev, int nrhs, int m, double rtol, int maxiters,
+                                      gnp_precision prec, gnp_solve_info *infos,
+                                      void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Training (Sec. 2.2 and Sec. 3 "Hyperparameters")                          */
 /* ------------------------------------------------------------------------ */

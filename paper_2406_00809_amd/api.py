@@ -227,6 +227,24 @@ def fgmres_solve(system: System, b: torch.Tensor, model: Model | None = None,
     return x, d, hist
 
 
+def fgmres_solve_batch(system: System, B: torch.Tensor, model: Model, X: torch.Tensor | None = None,
+                       m: int = 30, rtol: float = 1e-8, maxiters: int = 100, prec="bf16",
+                       stream=None):
+    """Solve A x_k = b_k for the rows of B ([nrhs, n], float64, device) in one
+    lockstep batch.  Returns (X, list of info dicts)."""
+    if B.dim() != 2 or B.shape[1] != system.n:
+        raise ValueError("B must have shape [nrhs, n]")
+    nrhs = B.shape[0]
+    if X is None:
+        X = torch.zeros_like(B)
+    infos = (SolveInfo * nrhs)()
+    check(_lib.load().fgmres_solve_batch(
+        system.handle, model.handle, _dev_ptr(B, torch.float64, nrhs * system.n, "B"),
+        _dev_ptr(X, torch.float64, nrhs * system.n, "X"), int(nrhs), int(m), float(rtol),
+        int(maxiters), PREC[prec], C.cast(infos, C.c_void_p), _stream(stream)))
+    return X, [infos[k].as_dict() for k in range(nrhs)]
+
+
 class Server:
     """Continuous-batching solve server (gnp_server_*): requests for any
     registered system are admitted into slots as slots and HBM free up and

@@ -460,14 +460,31 @@ __device__ __forceinline__ void layer_tiles(
                         }
                     }
                 } else {
+                    // (the same per-neighbour arithmetic as the staged path,
+                    // so that a row's result does not depend on its tile)
                     for (int32_t k = kbeg + ks; k < kbeg + ke; ++k) {
                         const uint32_t c = (uint32_t)ci[k];
-                        const acc_t a = Act<G>::wf(ahat[k]);
-                        acc_t xv[D / 4];
-                        load_feats<G, D / 4>(
-                            X + (c * (uint32_t)B + (uint32_t)b) * (uint32_t)D + q * (D / 4), xv);
+                        const G *xr =
+                            X + (c * (uint32_t)B + (uint32_t)b) * (uint32_t)D + q * (D / 4);
+                        if constexpr (sizeof(G) == 2) {
+                            constexpr int CB = (D / 4) * (int)sizeof(G);
+                            const Chunk<CB> raw = *reinterpret_cast<const Chunk<CB> *>(xr);
+                            const uint32_t wlo = (uint32_t)ahat[k], whi = wlo << 16;
 #pragma unroll
-                        for (int e = 0; e < D / 4; ++e) ta[e] += a * xv[e];
+                            for (int j = 0; j < CB / 4; ++j) {
+                                const bf16x2 xv = __builtin_bit_cast(bf16x2, raw.w[j]);
+                                ta[2 * j] = __builtin_amdgcn_fdot2_f32_bf16(
+                                    xv, __builtin_bit_cast(bf16x2, wlo), ta[2 * j], false);
+                                ta[2 * j + 1] = __builtin_amdgcn_fdot2_f32_bf16(
+                                    xv, __builtin_bit_cast(bf16x2, whi), ta[2 * j + 1], false);
+                            }
+                        } else {
+                            const acc_t a = Act<G>::wf(ahat[k]);
+                            acc_t xv[D / 4];
+                            load_feats<G, D / 4>(xr, xv);
+#pragma unroll
+                            for (int e = 0; e < D / 4; ++e) ta[e] += a * xv[e];
+                        }
                     }
                 }
             }

@@ -178,8 +178,10 @@ struct gnp_system {
     double *scratch = nullptr;                   // small reduction scratch
     int nscratch = 0;
     void *solve_cache = nullptr;                 // FGMRES workspace of fgmres_solve
+    void *batch_cache = nullptr;                 // workspace of fgmres_solve_batch
 };
 
 namespace gnp {
 void solve_cache_free(void *p);
+void batch_cache_free(void *p);
 }

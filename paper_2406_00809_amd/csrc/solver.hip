@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "solver.hpp"
 #include "spmv.hpp"
@@ -87,8 +88,10 @@ __device__ void reduce_columns(int nblk, int ncol, const double *__restrict__ pa
 // ||b||^2 partials and finalize
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_sumsq(int64_t n, const double *__restrict__ x,
-                                                 double *__restrict__ partial) {
+                                                 double *__restrict__ partial, Bat bt) {
     __shared__ double sh[BLOCK / WAVE];
+    x += blockIdx.y * bt.vec;
+    partial += blockIdx.y * bt.part;
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * BLOCK)
@@ -98,8 +101,10 @@ __global__ __launch_bounds__(BLOCK) void k_sumsq(int64_t n, const double *__rest
 }
 
 __global__ __launch_bounds__(BLOCK) void k_fin_bnorm(int nblk, const double *partial, double rtol,
-                                                     Ctl *ctl) {
+                                                     Ctl *ctl, Bat bt) {
     __shared__ double res[1];
+    partial += blockIdx.y * bt.part;
+    ctl += blockIdx.y;
     reduce_columns(nblk, 1, partial, 1, res);
     if (threadIdx.x == 0) {
         ctl->bnorm = sqrt(res[0]);
@@ -117,8 +122,12 @@ __global__ __launch_bounds__(BLOCK) void k_residual(int64_t n, const int32_t *__
                                                     const double *__restrict__ x,
                                                     const double *__restrict__ b,
                                                     double *__restrict__ r,
-                                                    double *__restrict__ partial) {
+                                                    double *__restrict__ partial, Bat bt) {
     __shared__ double sh[BLOCK / WAVE];
+    x += blockIdx.y * bt.vec;
+    b += blockIdx.y * bt.vec;
+    r += blockIdx.y * bt.vec;
+    partial += blockIdx.y * bt.part;
     const int lg = threadIdx.x % G;
     double s = 0.0;
     const int64_t stride = (int64_t)gridDim.x * (BLOCK / G);
@@ -140,12 +149,17 @@ __global__ __launch_bounds__(BLOCK) void k_residual(int64_t n, const int32_t *__
 
 // beta = ||r||; convergence / iteration-limit decision; restart bookkeeping
 __global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *partial, Ctl *ctl,
-                                                        double *g, double *hist, int initial) {
+                                                        double *g, double *hist, int initial,
+                                                        Bat bt) {
     __shared__ double res[1];
+    partial += blockIdx.y * bt.part;
+    ctl += blockIdx.y;
+    g += blockIdx.y * bt.small;
+    if (hist) hist += blockIdx.y * bt.hist;
     reduce_columns(nblk, 1, partial, 1, res);
     const double beta = sqrt(res[0]);
     if (threadIdx.x == 0) {
-        const double rel = beta / ctl->bnorm;
+        const double rel = ctl->bnorm > 0.0 ? beta / ctl->bnorm : 0.0;
         ctl->rel_true = rel;
         ctl->beta = beta;
         if (initial) {
@@ -179,16 +193,21 @@ __global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__rest
                                                      KT *__restrict__ V, int col,
                                                      KT *__restrict__ vcur,
                                                      double *__restrict__ partial, const Ctl *ctl,
-                                                     int use_beta) {
+                                                     int use_beta, Bat bt) {
+    const int bi = blockIdx.y;
+    ctl += bi;
     if (ctl->cycle_done) return;
     __shared__ double sh[BLOCK / WAVE];
+    src += bi * bt.vec;
+    V += bi * bt.basis;
+    partial += bi * bt.part;
     const double div = use_beta ? ctl->beta : ctl->hnext;
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * BLOCK) {
         const KT t = (KT)((double)src[i] / div);
         V[i * MP + col] = t;
-        vcur[i] = t;
+        vcur[i * bt.vstep + bi] = t;
         s += (double)t * (double)t;
     }
     s = block_sum(s, sh);
@@ -196,10 +215,22 @@ __global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__rest
 }
 
 // tau triple (tau, sqrt(n)/tau, tau/sqrt(n)) of the network input, Eq. (6)
+// In a batch (gridDim.y right-hand sides), block (0, 0) also records in
+// *all_done whether every right-hand side has ended its cycle (the network
+// launches of the next step are then skipped).
 __global__ __launch_bounds__(BLOCK) void k_fin_tau(int nblk, const double *partial, int64_t n,
-                                                   double *tau, const Ctl *ctl) {
+                                                   double *tau, const Ctl *ctl, Bat bt,
+                                                   int *all_done) {
+    if (all_done && blockIdx.y == 0 && threadIdx.x == 0) {
+        int done = 1;
+        for (int k = 0; k < (int)gridDim.y; ++k) done &= ctl[k].cycle_done ? 1 : 0;
+        *all_done = done;
+    }
+    ctl += blockIdx.y;
     if (ctl->cycle_done) return;
     __shared__ double res[1];
+    partial += blockIdx.y * bt.part;
+    tau += 3 * blockIdx.y;
     reduce_columns(nblk, 1, partial, 1, res);
     if (threadIdx.x == 0) {
         const double tv = sqrt(res[0]), sqn = sqrt((double)n);
@@ -235,8 +266,13 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, const KT 
                                                int j, KT *__restrict__ w,
                                                const double *__restrict__ hprev,
                                                double *__restrict__ partial, int pstride,
-                                               const Ctl *ctl) {
+                                               const Ctl *ctl, Bat bt) {
+    ctl += blockIdx.y;
     if (ctl->cycle_done) return;
+    V += blockIdx.y * bt.basis;
+    w += blockIdx.y * bt.vec;
+    if (hprev) hprev += blockIdx.y * bt.small;
+    partial += blockIdx.y * bt.part;
     constexpr int NU = MP / 32, NA = 4 * NU;
     const int t = threadIdx.x, q = t % 8, g = t / 8;
     const int64_t i0 = (int64_t)blockIdx.x * rpb;
@@ -338,8 +374,11 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, const KT 
 // dots finalize: hout[0..j] (and ||A z_j|| from the norm slot in MODE 0)
 template <int MODE>
 __global__ __launch_bounds__(BLOCK) void k_fin_dots(int nblk, int j, const double *partial,
-                                                    int pstride, double *hout, Ctl *ctl) {
+                                                    int pstride, double *hout, Ctl *ctl, Bat bt) {
+    ctl += blockIdx.y;
     if (ctl->cycle_done) return;
+    partial += blockIdx.y * bt.part;
+    hout += blockIdx.y * bt.small;
     __shared__ double res[MAXCOL];
     reduce_columns(nblk, j + 1, partial, pstride, res);
     for (int k = threadIdx.x; k <= j; k += BLOCK) hout[k] = res[k];
@@ -356,7 +395,20 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const dou
                                                       int pstride, const double *h1,
                                                       const double *h2, Ctl *ctl, double *H,
                                                       double *H0, double *cs, double *sn,
-                                                      double *g, double *hist) {
+                                                      double *g, double *hist, Bat bt) {
+    {
+        const int bi = blockIdx.y;
+        ctl += bi;
+        partial += bi * bt.part;
+        h1 += bi * bt.small;
+        h2 += bi * bt.small;
+        H += bi * bt.hess;
+        H0 += bi * bt.hess;
+        cs += bi * bt.small;
+        sn += bi * bt.small;
+        g += bi * bt.small;
+        if (hist) hist += bi * bt.hist;
+    }
     if (ctl->cycle_done) return;
     __shared__ double res[1];
     __shared__ double col[MAXCOL], scs[MAXCOL], ssn[MAXCOL];
@@ -421,7 +473,11 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const dou
 // y = R^{-1} g on the leading columns with nonzero pivots: the triangle and g
 // are staged in LDS by all threads, then one thread substitutes backwards.
 __global__ __launch_bounds__(BLOCK) void k_backsolve(Ctl *ctl, const double *H, const double *g,
-                                                     double *y) {
+                                                     double *y, Bat bt) {
+    ctl += blockIdx.y;
+    H += blockIdx.y * bt.hess;
+    g += blockIdx.y * bt.small;
+    y += blockIdx.y * bt.small;
     __shared__ double R[64 * 64];
     __shared__ double gs[64], ys[64];
     __shared__ int kk_s;
@@ -477,6 +533,29 @@ __global__ __launch_bounds__(BLOCK) void k_update_x(int64_t n, const KT *__restr
         else
             for (int k = 0; k < ku; ++k) acc += (double)Z[(int64_t)k * n + i] * y[k];
         x[i] += acc;
+    }
+}
+
+// x_b += Z_b y_b for a batch whose network outputs are packed: Zp holds step
+// k's outputs of all right-hand sides at Zp[k * n * nb + i * nb + b].  One
+// thread per (row, right-hand side), right-hand side fastest; the sum over k
+// runs in the order of k_update_x.
+template <typename KT>
+__global__ __launch_bounds__(BLOCK) void k_update_x_pk(int64_t n, int nb, const KT *__restrict__ Zp,
+                                                       const double *__restrict__ y,
+                                                       const Ctl *ctl, double *__restrict__ x,
+                                                       Bat bt) {
+    const int64_t total = n * nb;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * BLOCK) {
+        const int b = (int)(e % nb);
+        const int64_t i = e / nb;
+        const int ku = ctl[b].kuse;
+        if (ku == 0) continue;
+        const double *yb = y + b * bt.small;
+        double acc = 0.0;
+        for (int k = 0; k < ku; ++k) acc += (double)Zp[(int64_t)k * total + e] * yb[k];
+        x[b * bt.vec + i] += acc;
     }
 }
 
@@ -586,10 +665,10 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     const bool tau_in_encoder = model && c->prec != GNP_F64;
     const bool tau_kernel = model && !tau_in_encoder;
     hipLaunchKernelGGL((k_normalize<KT, double, MP>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, V, 0,
-                       vcur, c->partial, c->ctl, 1);
+                       vcur, c->partial, c->ctl, 1, Bat{});
     if (tau_kernel)
         hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
-                           c->ctl);
+                           c->ctl, Bat{}, (int *)nullptr);
     for (int j = 0; j < nsteps; ++j) {
         KT *zj = model ? Z + (int64_t)j * n : vcur;
         if (model)
@@ -598,28 +677,28 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
         spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
                            (const KT *)V, j, w, (const double *)nullptr, c->partial, pstride,
-                           (const Ctl *)c->ctl);
+                           (const Ctl *)c->ctl, Bat{});
         hipLaunchKernelGGL(k_fin_dots<0>, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
-                           (const double *)c->partial, pstride, c->h1, c->ctl);
+                           (const double *)c->partial, pstride, c->h1, c->ctl, Bat{});
         hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
                            (const KT *)V, j, w, (const double *)c->h1, c->partial, pstride,
-                           (const Ctl *)c->ctl);
+                           (const Ctl *)c->ctl, Bat{});
         hipLaunchKernelGGL(k_fin_dots<1>, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
-                           (const double *)c->partial, pstride, c->h2, c->ctl);
+                           (const double *)c->partial, pstride, c->h2, c->ctl, Bat{});
         hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
                            (const KT *)V, j, w, (const double *)c->h2, c->partial, pstride,
-                           (const Ctl *)c->ctl);
+                           (const Ctl *)c->ctl, Bat{});
         hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, (const double *)c->h1,
                            (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
-                           c->hist);
+                           c->hist, Bat{});
         hipLaunchKernelGGL((k_normalize<KT, KT, MP>), dim3(sg), dim3(BLOCK), 0, st, n,
-                           (const KT *)w, V, j + 1, vcur, c->partial, c->ctl, 0);
+                           (const KT *)w, V, j + 1, vcur, c->partial, c->ctl, 0, Bat{});
         if (tau_kernel)
             hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
-                               c->ctl);
+                               c->ctl, Bat{}, (int *)nullptr);
     }
-    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(BLOCK), 0, st, c->ctl, c->H, c->g, c->y);
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(BLOCK), 0, st, c->ctl, c->H, c->g, c->y, Bat{});
     if (model)
         hipLaunchKernelGGL((k_update_x<KT, MP, false>), dim3(sg), dim3(BLOCK), 0, st, n,
                            (const KT *)Z, c->y, c->ctl, x);
@@ -651,15 +730,15 @@ static void launch_residual(SolveCtx *c, const double *b, const double *x, int i
     const int grid = grid_for(n, BLOCK / G, 1024);
     if (G == 4)
         hipLaunchKernelGGL(k_residual<4>, dim3(grid), dim3(BLOCK), 0, st, n, s->rp, s->ci,
-                           s->val64, x, b, c->r, c->partial);
+                           s->val64, x, b, c->r, c->partial, Bat{});
     else if (G == 8)
         hipLaunchKernelGGL(k_residual<8>, dim3(grid), dim3(BLOCK), 0, st, n, s->rp, s->ci,
-                           s->val64, x, b, c->r, c->partial);
+                           s->val64, x, b, c->r, c->partial, Bat{});
     else
         hipLaunchKernelGGL(k_residual<16>, dim3(grid), dim3(BLOCK), 0, st, n, s->rp, s->ci,
-                           s->val64, x, b, c->r, c->partial);
+                           s->val64, x, b, c->r, c->partial, Bat{});
     hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(BLOCK), 0, st, grid,
-                       (const double *)c->partial, c->ctl, c->g, c->hist, initial);
+                       (const double *)c->partial, c->ctl, c->g, c->hist, initial, Bat{});
 }
 
 gnp_status solve_begin(SolveCtx *c, const double *b, const double *x, int m, double rtol,
@@ -672,9 +751,9 @@ gnp_status solve_begin(SolveCtx *c, const double *b, const double *x, int m, dou
     *c->ctl_host = init;
     GNP_HIP(hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
     const int sg = stream_grid(n);
-    hipLaunchKernelGGL(k_sumsq, dim3(sg), dim3(BLOCK), 0, st, n, b, c->partial);
+    hipLaunchKernelGGL(k_sumsq, dim3(sg), dim3(BLOCK), 0, st, n, b, c->partial, Bat{});
     hipLaunchKernelGGL(k_fin_bnorm, dim3(1), dim3(BLOCK), 0, st, sg, (const double *)c->partial,
-                       rtol, c->ctl);
+                       rtol, c->ctl, Bat{});
     launch_residual(c, b, x, 1, st);
     GNP_HIP(hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     return GNP_OK;
@@ -734,6 +813,239 @@ gnp_status solve_run(SolveCtx *c, gnp_model *model, const double *b, double *x, 
     return GNP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched solve: nb right-hand sides of one system in lockstep.  Every solver
+// kernel runs once per stage with gridDim.y = nb on per-right-hand-side
+// slices (Bat strides); the network input of all right-hand sides is packed
+// [n][nb] so that one network launch per step serves the whole batch, and
+// the network outputs stay packed (Zp) for the update of x.  Each right-hand
+// side follows the single-solve arithmetic step for step.
+// ---------------------------------------------------------------------------
+struct BatchCtx {
+    gnp_system *sys = nullptr;
+    int m = 0, mp = 32, nb = 0, cap = 0, d = 0;
+    gnp_precision prec = GNP_BF16;
+    int64_t n = 0, npartial = 0;
+    float *V = nullptr, *Zp = nullptr, *vpk = nullptr, *w = nullptr;
+    void *act[2] = {nullptr, nullptr};
+    double *r = nullptr, *tau = nullptr, *H = nullptr, *H0 = nullptr, *cs = nullptr,
+           *sn = nullptr, *g = nullptr, *y = nullptr, *h1 = nullptr, *h2 = nullptr,
+           *hist = nullptr, *partial = nullptr;
+    Ctl *ctl = nullptr, *ctl_host = nullptr;
+    int *all_done = nullptr;
+    Bat bt;
+};
+
+static void batch_free(BatchCtx *c) {
+    if (!c) return;
+    void *ptrs[] = {c->V,  c->Zp, c->vpk, c->w,  c->act[0], c->act[1], c->r,  c->tau,
+                    c->H,  c->H0, c->cs,  c->sn, c->g,      c->y,      c->h1, c->h2,
+                    c->hist, c->partial, c->ctl, c->all_done};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (c->ctl_host) (void)hipHostFree(c->ctl_host);
+    *c = BatchCtx();
+}
+
+static gnp_status batch_prepare(BatchCtx *c, gnp_system *sys, int m, int maxiters, int nb,
+                                int d) {
+    if (c->sys == sys && c->m == m && c->nb == nb && c->cap >= maxiters && c->d == d)
+        return GNP_OK;
+    batch_free(c);
+    const int64_t n = sys->n;
+    c->sys = sys;
+    c->m = m;
+    c->mp = basis_pitch(m);
+    c->nb = nb;
+    c->cap = std::max(maxiters, 128);
+    c->d = d;
+    c->n = n;
+    const int64_t nb_cgs = (n + cgs_rpb(n) - 1) / cgs_rpb(n);
+    c->npartial = std::max<int64_t>(nb_cgs * (c->mp + 1), 2048);
+    c->bt.vec = n;
+    c->bt.basis = n * c->mp;
+    c->bt.part = c->npartial;
+    c->bt.hess = (int64_t)(m + 1) * m;
+    c->bt.small = m + 1;
+    c->bt.hist = c->cap + 1;
+    c->bt.vstep = nb;
+    auto al = [&](auto **q, size_t count) -> gnp_status {
+        GNP_HIP(hipMalloc((void **)q, sizeof(**q) * count));
+        return GNP_OK;
+    };
+    GNP_TRY(al(&c->V, (size_t)nb * n * c->mp));
+    GNP_HIP(hipMemset(c->V, 0, sizeof(float) * (size_t)nb * n * c->mp));
+    GNP_TRY(al(&c->Zp, (size_t)m * n * nb));
+    GNP_TRY(al(&c->vpk, (size_t)n * nb));
+    GNP_TRY(al(&c->w, (size_t)n * nb));
+    for (int i = 0; i < 2; ++i) GNP_HIP(hipMalloc(&c->act[i], sizeof(float) * n * nb * d));
+    GNP_TRY(al(&c->r, (size_t)n * nb));
+    GNP_TRY(al(&c->tau, (size_t)3 * nb));
+    GNP_TRY(al(&c->H, (size_t)nb * c->bt.hess));
+    GNP_TRY(al(&c->H0, (size_t)nb * c->bt.hess));
+    for (double **q : {&c->cs, &c->sn, &c->g, &c->y, &c->h1, &c->h2})
+        GNP_TRY(al(q, (size_t)nb * c->bt.small));
+    GNP_TRY(al(&c->hist, (size_t)nb * c->bt.hist));
+    GNP_TRY(al(&c->partial, (size_t)nb * c->npartial));
+    GNP_TRY(al(&c->ctl, (size_t)nb));
+    GNP_TRY(al(&c->all_done, 1));
+    GNP_HIP(hipHostMalloc(&c->ctl_host, sizeof(Ctl) * nb, hipHostMallocDefault));
+    return GNP_OK;
+}
+
+template <int MP>
+static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double *x,
+                              hipStream_t st) {
+    gnp_system *s = c->sys;
+    const int64_t n = s->n;
+    const int nb = c->nb;
+    const Bat &bt = c->bt;
+    const int sg = stream_grid(n);
+    const int64_t rpb = cgs_rpb(n);
+    const int gcgs = (int)((n + rpb - 1) / rpb);
+    const int pstride = MP + 1;
+    float *V = c->V, *w = c->w;
+    hipLaunchKernelGGL((k_normalize<float, double, MP>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
+                       (const double *)c->r, V, 0, c->vpk, c->partial, (const Ctl *)c->ctl, 1, bt);
+    hipLaunchKernelGGL(k_fin_tau, dim3(1, nb), dim3(BLOCK), 0, st, sg, (const double *)c->partial,
+                       n, c->tau, (const Ctl *)c->ctl, bt, c->all_done);
+    for (int j = 0; j < nsteps; ++j) {
+        float *zj = c->Zp + (int64_t)j * n * nb;
+        GNP_TRY(forward_launch(model, c->prec, c->vpk, zj, nb, c->tau, c->act[0], c->act[1],
+                               c->all_done, st));
+        spmv_launch<float, float, float>(n, s->rp, s->ci, s->val32, zj, w, nullptr,
+                                         &c->ctl->cycle_done, s->nnz, st, nb, nb, n,
+                                         (int)(sizeof(Ctl) / sizeof(int)));
+        hipLaunchKernelGGL((k_cgs<float, MP, 0>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb,
+                           (const float *)V, j, w, (const double *)nullptr, c->partial, pstride,
+                           (const Ctl *)c->ctl, bt);
+        hipLaunchKernelGGL(k_fin_dots<0>, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, c->h1, c->ctl, bt);
+        hipLaunchKernelGGL((k_cgs<float, MP, 1>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb,
+                           (const float *)V, j, w, (const double *)c->h1, c->partial, pstride,
+                           (const Ctl *)c->ctl, bt);
+        hipLaunchKernelGGL(k_fin_dots<1>, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, c->h2, c->ctl, bt);
+        hipLaunchKernelGGL((k_cgs<float, MP, 2>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb,
+                           (const float *)V, j, w, (const double *)c->h2, c->partial, pstride,
+                           (const Ctl *)c->ctl, bt);
+        hipLaunchKernelGGL(k_fin_givens, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, (const double *)c->h1,
+                           (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
+                           c->hist, bt);
+        hipLaunchKernelGGL((k_normalize<float, float, MP>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
+                           (const float *)w, V, j + 1, c->vpk, c->partial, (const Ctl *)c->ctl, 0,
+                           bt);
+        hipLaunchKernelGGL(k_fin_tau, dim3(1, nb), dim3(BLOCK), 0, st, sg,
+                           (const double *)c->partial, n, c->tau, (const Ctl *)c->ctl, bt,
+                           c->all_done);
+    }
+    hipLaunchKernelGGL(k_backsolve, dim3(1, nb), dim3(BLOCK), 0, st, c->ctl, (const double *)c->H,
+                       (const double *)c->g, c->y, bt);
+    hipLaunchKernelGGL((k_update_x_pk<float>), dim3(grid_for(n * nb, BLOCK, 4096)), dim3(BLOCK), 0,
+                       st, n, nb, (const float *)c->Zp, (const double *)c->y, (const Ctl *)c->ctl,
+                       x, bt);
+    GNP_HIP(hipGetLastError());
+    return GNP_OK;
+}
+
+static void batch_residual(BatchCtx *c, const double *b, const double *x, int initial,
+                           hipStream_t st) {
+    gnp_system *s = c->sys;
+    const int64_t n = s->n;
+    const double avg = (double)s->nnz / (double)n;
+    const int G = avg <= 12.0 ? 4 : (avg <= 24.0 ? 8 : 16);
+    const int grid = grid_for(n, BLOCK / G, 1024);
+    const dim3 gg(grid, c->nb);
+    if (G == 4)
+        hipLaunchKernelGGL(k_residual<4>, gg, dim3(BLOCK), 0, st, n, s->rp, s->ci, s->val64, x, b,
+                           c->r, c->partial, c->bt);
+    else if (G == 8)
+        hipLaunchKernelGGL(k_residual<8>, gg, dim3(BLOCK), 0, st, n, s->rp, s->ci, s->val64, x, b,
+                           c->r, c->partial, c->bt);
+    else
+        hipLaunchKernelGGL(k_residual<16>, gg, dim3(BLOCK), 0, st, n, s->rp, s->ci, s->val64, x,
+                           b, c->r, c->partial, c->bt);
+    hipLaunchKernelGGL(k_fin_residual, dim3(1, c->nb), dim3(BLOCK), 0, st, grid,
+                       (const double *)c->partial, c->ctl, c->g, c->hist, initial, c->bt);
+}
+
+static gnp_status batch_run(BatchCtx *c, gnp_model *model, const double *b, double *x, int m,
+                            double rtol, int maxiters, gnp_solve_info *infos, hipStream_t st) {
+    const int64_t n = c->n;
+    const int nb = c->nb;
+    Ctl init;
+    memset(&init, 0, sizeof(init));
+    init.m = m;
+    init.maxiters = maxiters;
+    for (int k = 0; k < nb; ++k) c->ctl_host[k] = init;
+    GNP_HIP(hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl) * nb, hipMemcpyHostToDevice, st));
+    const int sg = stream_grid(n);
+    hipLaunchKernelGGL(k_sumsq, dim3(sg, nb), dim3(BLOCK), 0, st, n, b, c->partial, c->bt);
+    hipLaunchKernelGGL(k_fin_bnorm, dim3(1, nb), dim3(BLOCK), 0, st, sg, (const double *)c->partial,
+                       rtol, c->ctl, c->bt);
+    batch_residual(c, b, x, 1, st);
+    GNP_HIP(hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl) * nb, hipMemcpyDeviceToHost, st));
+    GNP_HIP(hipStreamSynchronize(st));
+    bool zero_rhs = false;
+    for (int k = 0; k < nb; ++k) {
+        Ctl &h = c->ctl_host[k];
+        if (!std::isfinite(h.bnorm)) return fail(GNP_ENUMERIC, "a right-hand side is not finite");
+        if (h.bnorm == 0.0) {  // x = 0, nothing to iterate
+            GNP_HIP(hipMemsetAsync(x + (int64_t)k * n, 0, sizeof(double) * n, st));
+            h.converged = 1;
+            h.solve_done = 1;
+            h.cycle_done = 1;
+            h.rel_true = 0.0;
+            h.est_rel = 0.0;
+            zero_rhs = true;
+        }
+    }
+    if (zero_rhs)
+        GNP_HIP(hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl) * nb, hipMemcpyHostToDevice, st));
+    auto all_done = [&]() {
+        for (int k = 0; k < nb; ++k)
+            if (!c->ctl_host[k].solve_done) return false;
+        return true;
+    };
+    std::vector<int> it0(nb);
+    while (!all_done()) {
+        int nsteps = 0;
+        for (int k = 0; k < nb; ++k) {
+            it0[k] = c->ctl_host[k].it;
+            if (!c->ctl_host[k].solve_done) nsteps = std::max(nsteps, std::min(m, maxiters - it0[k]));
+        }
+        switch (c->mp) {
+            case 32: GNP_TRY(batch_cycle<32>(c, model, nsteps, x, st)); break;
+            case 64: GNP_TRY(batch_cycle<64>(c, model, nsteps, x, st)); break;
+            case 128: GNP_TRY(batch_cycle<128>(c, model, nsteps, x, st)); break;
+            case 256: GNP_TRY(batch_cycle<256>(c, model, nsteps, x, st)); break;
+            default: return fail(GNP_EINVAL, "unsupported basis pitch");
+        }
+        batch_residual(c, b, x, 0, st);
+        GNP_HIP(hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(Ctl) * nb, hipMemcpyDeviceToHost, st));
+        GNP_HIP(hipStreamSynchronize(st));
+        bool progress = false;
+        for (int k = 0; k < nb; ++k)
+            if (c->ctl_host[k].it > it0[k] || c->ctl_host[k].solve_done) progress = true;
+        if (!progress) return fail(GNP_EDEVICE, "batched solver made no progress in a cycle");
+    }
+    bool nonfinite = false;
+    for (int k = 0; k < nb; ++k) {
+        solve_info_from(c->ctl_host[k], infos ? infos + k : nullptr);
+        nonfinite |= c->ctl_host[k].nonfinite != 0;
+    }
+    if (nonfinite) return fail(GNP_ENUMERIC, "non-finite value in the Arnoldi process");
+    return GNP_OK;
+}
+
+void batch_cache_free(void *p) {
+    if (!p) return;
+    BatchCtx *c = (BatchCtx *)p;
+    batch_free(c);
+    delete c;
+}
+
 }  // namespace gnp
 
 using namespace gnp;
@@ -754,6 +1066,25 @@ extern "C" gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const doub
     c->prec = prec;
     return solve_run(c, model, b_dev, x_dev, m, rtol, maxiters, hist, info,
                      (hipStream_t)hip_stream);
+}
+
+extern "C" gnp_status fgmres_solve_batch(gnp_system *sys, gnp_model *model, const double *b_dev,
+                                         double *x_dev, int nrhs, int m, double rtol,
+                                         int maxiters, gnp_precision prec, gnp_solve_info *infos,
+                                         void *hip_stream) {
+    if (!sys || !model || !b_dev || !x_dev) return fail(GNP_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > 256) return fail(GNP_EINVAL, "nrhs must be in [1, 256]");
+    if (m < 1 || m > 255) return fail(GNP_EINVAL, "m must be in [1, 255]");
+    if (!(rtol > 0.0)) return fail(GNP_EINVAL, "rtol must be > 0");
+    if (maxiters < 1) return fail(GNP_EINVAL, "maxiters must be >= 1");
+    if (prec != GNP_F32 && prec != GNP_BF16)
+        return fail(GNP_EINVAL, "batched solves run the float32 or bfloat16 network");
+    if (model->sys != sys) return fail(GNP_EINVAL, "model belongs to another system");
+    if (!sys->batch_cache) sys->batch_cache = new BatchCtx();
+    BatchCtx *c = (BatchCtx *)sys->batch_cache;
+    GNP_TRY(batch_prepare(c, sys, m, maxiters, nrhs, model->d));
+    c->prec = prec;
+    return batch_run(c, model, b_dev, x_dev, m, rtol, maxiters, infos, (hipStream_t)hip_stream);
 }
 
 namespace gnp {

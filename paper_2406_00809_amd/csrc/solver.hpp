@@ -22,6 +22,19 @@ struct Ctl {
     double bnorm, target, beta, est, rel_true, wnorm0, hnext, est_rel;
 };
 
+// Per-right-hand-side strides (elements) of a batched solve: right-hand
+// side b = blockIdx.y of every solver kernel works on its own slices.  All
+// zero (and vstep = 1) for a single solve.
+struct Bat {
+    int64_t vec = 0;    // n-vectors: b, x, r, w
+    int64_t basis = 0;  // Krylov basis V (n * MP)
+    int64_t part = 0;   // per-block partial sums
+    int64_t hess = 0;   // H, H0 ((m + 1) * m)
+    int64_t small = 0;  // cs, sn, g, y, h1, h2 (m + 1)
+    int64_t hist = 0;   // residual history
+    int vstep = 1;      // stride of the network input vector (nrhs when packed [n][nrhs])
+};
+
 struct SolveCtx {
     gnp_system *sys = nullptr;
     int m = 0;

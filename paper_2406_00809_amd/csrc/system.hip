@@ -187,6 +187,7 @@ static void sys_free(gnp_system *s) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     solve_cache_free(s->solve_cache);
+    batch_cache_free(s->batch_cache);
     delete s;
 }
 
