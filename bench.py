@@ -369,6 +369,20 @@ def main():
             its.append(inf5["iters"])
         st = srv.stats()
         srv.close()
+        # the same 32 right-hand sides as one lockstep batch (one network
+        # application per Arnoldi step for all of them)
+        Bt = torch.as_tensor(np.stack(bs), dtype=torch.float64, device=dev)
+        api.fgmres_solve_batch(S, Bt, M, m=m, rtol=1e-8, maxiters=args.maxiters, prec=args.prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, binfos = api.fgmres_solve_batch(S, Bt, M, m=m, rtol=1e-8, maxiters=args.maxiters,
+                                           prec=args.prec)
+        torch.cuda.synchronize()
+        batched = nb / (time.perf_counter() - t1)
+        extra["rhs32_batched"] = {"solves_per_s": batched,
+                                  "converged": int(sum(i["converged"] for i in binfos)),
+                                  "max_iters": int(max(i["iters"] for i in binfos))}
+        log(f"32 rhs batched {args.prec}: {batched:.2f}/s")
         extra["rhs32_fp32_single_solves_sequential"] = {"solves_per_s": seq, "converged": conv32}
         extra["rhs32_served_concurrent"] = {"solves_per_s": served, "converged": convs,
                                             "mean_iters": float(np.mean(its)),
