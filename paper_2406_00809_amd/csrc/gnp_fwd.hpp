@@ -90,6 +90,37 @@ __device__ __forceinline__ void store4<uint16_t>(uint16_t *p, float a, float b, 
 
 template <typename T> __device__ __forceinline__ T relu(T x) { return x > (T)0 ? x : (T)0; }
 
+// ReLU of two features rounded to bf16 (RNE) and packed: the rounding keeps
+// the sign, so clearing negative halves of the rounded pair equals rounding
+// the ReLU (a NaN keeps or loses its value with its sign bit).
+__device__ __forceinline__ uint32_t relu_pk_bf16(float a, float b) {
+    typedef __bf16 bf16v2 __attribute__((ext_vector_type(2)));
+    typedef float f32v2 __attribute__((ext_vector_type(2)));
+    typedef short i16v2 __attribute__((ext_vector_type(2)));
+    const bf16v2 h = __builtin_convertvector((f32v2){a, b}, bf16v2);
+    const i16v2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16v2, h), z));
+}
+
+// Buffer resource over `bytes` bytes at p (raw, stride 0): a load whose
+// offset lies past `bytes` returns zeros instead of touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+constexpr uint32_t BUF_OOB = 0xFFFFFFF0u;  // an offset past any buffer here (< 2^32 - 16 bytes)
+
+template <int BYTES>
+__device__ __forceinline__ Chunk<BYTES> buffer_chunk(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (BYTES == 16)
+        return __builtin_bit_cast(Chunk<16>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    else if constexpr (BYTES == 8)
+        return __builtin_bit_cast(Chunk<8>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else {
+        static_assert(BYTES == 4, "chunk of 4, 8 or 16 bytes");
+        return __builtin_bit_cast(Chunk<4>, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+}
+
 // Every LDS region of these kernels belongs to one wavefront, and a
 // wavefront's LDS operations execute in order, so a wavefront-scope fence
 // (ordering for the compiler) replaces a block barrier between the write and
@@ -638,6 +669,221 @@ __device__ __forceinline__ void layer_tiles(
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 Res-GCONV layer (Eq. (5)) without the decoder, pipelined so that a tile
+// costs one memory round trip: while tile t is gathered, the colind / value
+// slice of tile t + nw and the rowptr slice of tile t + 2 nw are already in
+// flight (issued just before the gather, so that the single wait for the
+// gather covers them too), and the tile's own CSR slice was fetched during the
+// previous tile.  All loads are unconditional (clamped addresses, results
+// unused when out of range), so the compiler can count them.  The rowptr
+// slice stays in registers (cross-lane reads), the MFMA weight fragments are
+// staged in LDS once per block.
+// ---------------------------------------------------------------------------
+template <int D, int H>
+__device__ __forceinline__ void layer_tiles_bf16(
+    int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const uint16_t *__restrict__ ahat, const uint16_t *__restrict__ X, uint16_t *__restrict__ Y,
+    const void *__restrict__ wcat, const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    using G = uint16_t;
+    constexpr int LD = 2 * D + lds_pad<G>();
+    constexpr int CAP = 256, NC = CAP / WAVE;
+    constexpr int KB = 2 * D / 32, NT = D / 16;  // MFMA k-blocks and n-tiles
+    constexpr int CB = (D / 4) * (int)sizeof(G);  // bytes per lane per row
+    constexpr int NB = 8;                         // neighbour loads per batch
+    __shared__ __attribute__((aligned(16))) G As[BLOCK / WAVE][16][LD];
+    __shared__ uint32_t sCo[BLOCK / WAVE][CAP];  // byte offset of row (column, rhs 0) in X
+    __shared__ uint16_t sVa[BLOCK / WAVE][CAP];
+    __shared__ __attribute__((aligned(16))) uint16_t sW[KB * NT * WAVE * 8];
+    const int lane = threadIdx.x % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(wcat);
+        for (int e = threadIdx.x; e < KB * NT * WAVE; e += BLOCK)
+            reinterpret_cast<uint4 *>(sW)[e] = src[e];
+        __syncthreads();
+    }
+    const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv);
+    const int64_t ntiles = walk.end, nw = walk.stride;
+    const uint32_t rowbytes = (uint32_t)B * (uint32_t)(D * sizeof(G));
+    const int rshift = (rowbytes & (rowbytes - 1)) == 0 ? __builtin_ctz(rowbytes) : -1;
+    // X holds rows * D features (< 2^32 bytes)
+    const __amdgpu_buffer_rsrc_t xr = buffer_rsrc(X, (uint32_t)rows * (uint32_t)(D * sizeof(G)));
+
+    // nodes of tile t (clamped to the last tile, so that a wave past the end
+    // loads valid addresses whose results it never uses); row indices fit in
+    // 32 bits because rows * D * sizeof(G) < 2^32
+    auto node_range = [&](int64_t t, uint32_t &ifirst, int &nn) {
+        const uint32_t tt = (uint32_t)(t < ntiles ? t : ntiles - 1);
+        const uint32_t r0 = tt * 16u;
+        const uint32_t rlast = r0 + 15u < (uint32_t)rows ? r0 + 15u : (uint32_t)rows - 1u;
+        ifirst = r0 / (uint32_t)B;
+        nn = (int)(rlast / (uint32_t)B - ifirst) + 1;
+    };
+    auto fetch_rp = [&](int64_t t) -> int32_t {
+        uint32_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        return rp[ifirst + (uint32_t)(lane <= nn ? lane : nn)];
+    };
+    // colind / value slice of tile t (rowptr slice rpv) into registers; lanes
+    // past the slice re-read its last entry (an empty slice reads the entry
+    // before it, or entry 0: nnz >= 1)
+    // entry range [kbeg, kbeg + cnt) of tile t from its rowptr slice rpv
+    // (wave-uniform results)
+    auto slice_range = [&](int64_t t, int32_t rpv, int32_t &kbeg, int32_t &cnt) {
+        uint32_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        kbeg = __builtin_amdgcn_readfirstlane(rpv);
+        cnt = __builtin_amdgcn_readlane(rpv, nn) - kbeg;
+    };
+    // colind / value slice [kbeg, kbeg + cnt) into registers; lanes past the
+    // slice re-read its last entry (an empty slice reads the entry before
+    // it, or entry 0: nnz >= 1)
+    auto fetch_csr = [&](int32_t kbeg, int32_t cnt, int32_t (&cv)[NC], uint16_t (&av)[NC]) {
+        const int32_t base = cnt > 0 ? kbeg : (kbeg > 0 ? kbeg - 1 : 0);
+        const int32_t lim = cnt > 0 ? cnt - 1 : 0;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            const int idx = lane + WAVE * u;
+            const uint32_t k = (uint32_t)(base + (idx < lim ? idx : lim));
+            cv[u] = ci[k];
+            av[u] = ahat[k];
+        }
+    };
+    // a slice of at most CAP entries goes to LDS as byte offsets and weights
+    auto commit = [&](int32_t cnt, const int32_t (&cv)[NC], const uint16_t (&av)[NC]) {
+        if (cnt <= CAP) {
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                const int idx = lane + WAVE * u;
+                sCo[wv][idx] = rshift >= 0 ? (uint32_t)cv[u] << rshift : (uint32_t)cv[u] * rowbytes;
+                sVa[wv][idx] = av[u];
+            }
+        }
+    };
+
+    // Prologue: tile t's slice in LDS, tile t + nw's rowptr slice and entry
+    // range known.  Everything loaded here is consumed here, so the loop
+    // starts with no loads in flight.
+    int64_t t = walk.t;
+    int32_t rp0 = fetch_rp(t);  // rowptr slice of the current tile
+    int32_t kb0, cnt0;          // its entry range
+    slice_range(t, rp0, kb0, cnt0);
+    int32_t rp1 = fetch_rp(t + nw);  // of the next tile
+    {
+        int32_t cv[NC];
+        uint16_t av[NC];
+        fetch_csr(kb0, cnt0, cv, av);
+        commit(cnt0, cv, av);
+    }
+    int32_t kb1, cnt1;
+    slice_range(t + nw, rp1, kb1, cnt1);
+    wave_lds_sync();
+    for (; t < ntiles; t += nw) {
+        const int64_t r0 = t * 16;
+        uint32_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        const int32_t kbeg = kb0;
+        const bool staged = cnt0 <= CAP;
+        // ---- next tiles' slices, in flight during this tile's gather
+        int32_t cv1[NC];
+        uint16_t av1[NC];
+        fetch_csr(kb1, cnt1, cv1, av1);
+        const int32_t rp2 = fetch_rp(t + 2 * nw);
+        // ---- gather T = A-hat X and the row's own X into the LDS tile
+        {
+            const int rl = lane / 4, q = lane % 4;
+            const int64_t r = r0 + rl;
+            const bool valid = r < rows;
+            const uint32_t rr = (uint32_t)(valid ? r : r0);
+            const uint32_t i = rr / (uint32_t)B;
+            const uint32_t b = rr - i * (uint32_t)B;
+            const int li = (int)(i - ifirst);
+            const int32_t ks = valid ? __shfl(rp0, li, WAVE) - kbeg : 0;
+            const int32_t ke = valid ? __shfl(rp0, li + 1, WAVE) - kbeg : 0;
+            const uint32_t lane_off = (b * D + (uint32_t)(q * (D / 4))) * (uint32_t)sizeof(G);
+            const uint32_t own_off = (rr * D + (uint32_t)(q * (D / 4))) * (uint32_t)sizeof(G);
+            // rows past the end read zeros
+            const Chunk<CB> own = buffer_chunk<CB>(xr, valid ? own_off : BUF_OOB);
+            float ta[D / 4];
+#pragma unroll
+            for (int e = 0; e < D / 4; ++e) ta[e] = 0.f;
+            auto acc_chunk = [&](const Chunk<CB> &raw, uint32_t wlo) {
+                const uint32_t whi = wlo << 16;
+#pragma unroll
+                for (int j = 0; j < CB / 4; ++j) {
+                    const bf16x2 xv = __builtin_bit_cast(bf16x2, raw.w[j]);
+                    ta[2 * j] = __builtin_amdgcn_fdot2_f32_bf16(xv, __builtin_bit_cast(bf16x2, wlo),
+                                                                ta[2 * j], false);
+                    ta[2 * j + 1] = __builtin_amdgcn_fdot2_f32_bf16(
+                        xv, __builtin_bit_cast(bf16x2, whi), ta[2 * j + 1], false);
+                }
+            };
+            if (staged) {
+                for (int32_t k0 = ks; k0 < ke; k0 += NB) {
+                    Chunk<CB> raw[NB];
+                    uint32_t wgt[NB];
+                    // slots past the row read zeros: their (finite, staged)
+                    // weights then add nothing
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const int32_t kk = k0 + u < CAP ? k0 + u : CAP - 1;
+                        wgt[u] = sVa[wv][kk];
+                        raw[u] = buffer_chunk<CB>(xr, k0 + u < ke ? sCo[wv][kk] + lane_off : BUF_OOB);
+                    }
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) acc_chunk(raw[u], wgt[u]);
+                }
+            } else {
+                for (int32_t k = kbeg + ks; k < kbeg + ke; ++k) {
+                    const uint32_t c = (uint32_t)ci[k];
+                    acc_chunk(buffer_chunk<CB>(xr, c * rowbytes + lane_off), (uint32_t)ahat[k]);
+                }
+            }
+            *reinterpret_cast<Chunk<CB> *>(&As[wv][rl][q * (D / 4)]) = own;  // already bf16
+            store_feats<G, D / 4>(&As[wv][rl][D + q * (D / 4)], ta);
+        }
+        wave_lds_sync();
+        // ---- Y^T = [U; W]^T [X | T]^T on MFMA, lane gets row l % 16
+        {
+            f32x4 o[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) o[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const bf16x8 xf = load_bf16x8(&As[wv][lane % 16][kb * 32 + 8 * (lane / 16)]);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    o[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        load_bf16x8(sW + ((kb * NT + nt) * WAVE + lane) * 8), xf, o[nt], 0, 0, 0);
+            }
+            const int64_t r = r0 + lane % 16;
+            if (r < rows) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    *reinterpret_cast<uint2 *>(Y + r * D + nt * 16 + 4 * (lane / 16)) =
+                        make_uint2(relu_pk_bf16(o[nt][0], o[nt][1]), relu_pk_bf16(o[nt][2], o[nt][3]));
+            }
+        }
+        // ---- the next tile's slice to LDS (this tile's gather has read its
+        // own), the entry range of the one after
+        commit(cnt1, cv1, av1);
+        int32_t kb2, cnt2;
+        slice_range(t + 2 * nw, rp2, kb2, cnt2);
+        wave_lds_sync();
+        rp0 = rp1;
+        rp1 = rp2;
+        kb0 = kb1;
+        cnt0 = cnt1;
+        kb1 = kb2;
+        cnt1 = cnt2;
+    }
+}
+
 #define GNP_LAYER_PARAMS                                                                       \
     int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,       \
         const typename Act<G>::vt *__restrict__ ahat, const G *__restrict__ X,                 \
@@ -657,7 +903,10 @@ __global__ __launch_bounds__(BLOCK) void k_layer(GNP_LAYER_PARAMS) {
 template <typename G, int D, int H, typename ZT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_layer_w4(
     GNP_LAYER_PARAMS) {
-    layer_tiles<G, D, H, false, ZT>(GNP_LAYER_ARGS);
+    if constexpr (sizeof(G) == 2)
+        layer_tiles_bf16<D, H>(rows, B, rp, ci, ahat, X, Y, wcat, skip);
+    else
+        layer_tiles<G, D, H, false, ZT>(GNP_LAYER_ARGS);
 }
 #undef GNP_LAYER_PARAMS
 #undef GNP_LAYER_ARGS
