@@ -36,46 +36,44 @@ static int stream_grid(int64_t n) { return grid_for(n, 4 * BLOCK, 1024); }
 
 // ---------------------------------------------------------------------------
 // one-block finalize helper: out[c] = sum over blk < nblk of
-// partial[blk * stride + c] for c < ncol, fixed summation order.
+// partial[blk * stride + c] for c < ncol, and with extra >= 0 also
+// out[ncol] = the same sum of column `extra`; fixed summation order.
 // ---------------------------------------------------------------------------
 __device__ void reduce_columns(int nblk, int ncol, const double *__restrict__ partial, int stride,
-                               double *out /* shared, >= ncol */) {
+                               double *out /* shared, >= ncol + 1 */, int extra = -1) {
     __shared__ double sh[BLOCK];
     const int t = threadIdx.x;
-    if (ncol == 1) {
-        const double s = sum_partials(nblk, partial, stride, sh);
+    const int nc = ncol + (extra >= 0 ? 1 : 0);
+    if (nc == 1) {
+        const double s = sum_partials(nblk, partial + (ncol == 1 ? 0 : extra), stride, sh);
         if (t == 0) out[0] = s;
         __syncthreads();
         return;
     }
-    // lanes over columns (CP per chunk), the rest over block subsets; each
-    // thread keeps 16 independent loads in flight per round
-    const int CP = ncol <= 32 ? 32 : 64;
+    // lanes over output columns (CP per chunk), the rest over block subsets;
+    // each thread issues all its loads of a round (U) before adding them in
+    // block order: one memory round trip for up to S * U blocks
+    constexpr int U = 64;
+    const int CP = nc <= 32 ? 32 : 64;
     const int S = BLOCK / CP;
     const int cl = t % CP, sub = t / CP;
-    for (int c0 = 0; c0 < ncol; c0 += CP) {
-        const int col = c0 + cl;
-        double a[16];
+    for (int c0 = 0; c0 < nc; c0 += CP) {
+        const int oc = c0 + cl;
+        const int src = oc < ncol ? oc : (oc == ncol && extra >= 0 ? extra : 0);
+        double s = 0.0;
+        for (int blk0 = sub * U; blk0 < nblk; blk0 += S * U) {
+            double v[U];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) a[u] = 0.0;
-        const int colc = col < ncol ? col : ncol - 1;
-        for (int blk0 = sub * 16; blk0 < nblk; blk0 += S * 16) {
-            // clamped, unconditional loads: all 16 in flight before the adds
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < U; ++u) {  // clamped, unconditional loads
                 const int blk = (blk0 + u < nblk) ? blk0 + u : nblk - 1;
-                v[u] = partial[(int64_t)blk * stride + colc];
+                v[u] = partial[(int64_t)blk * stride + src];
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) a[u] += (blk0 + u < nblk && col < ncol) ? v[u] : 0.0;
+            for (int u = 0; u < U; ++u) s += (blk0 + u < nblk && oc < nc) ? v[u] : 0.0;
         }
-        double s = 0.0;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) s += a[u];
         sh[t] = s;
         __syncthreads();
-        if (t < CP && c0 + t < ncol) {
+        if (t < CP && c0 + t < nc) {
             double v = 0.0;
             for (int q = 0; q < S; ++q) v += sh[q * CP + t];
             out[c0 + t] = v;
@@ -185,12 +183,13 @@ __global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *
 }
 
 // ---------------------------------------------------------------------------
-// v = src / div into basis column `col` and vcur; partial ||v||^2 of the
-// stored (rounded) values.  div = beta (cycle start) or h_{j+1,j}.
+// v = src / div into vcur (contiguous); partial ||v||^2 of the stored
+// (rounded) values.  div = beta (cycle start) or h_{j+1,j}.  The basis
+// column of v is written by the next step's first Gram-Schmidt pass, which
+// reads that row of the basis anyway.
 // ---------------------------------------------------------------------------
-template <typename KT, typename ST, int MP>
+template <typename KT, typename ST>
 __global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__restrict__ src,
-                                                     KT *__restrict__ V, int col,
                                                      KT *__restrict__ vcur,
                                                      double *__restrict__ partial, const Ctl *ctl,
                                                      int use_beta, Bat bt) {
@@ -199,14 +198,12 @@ __global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__rest
     if (ctl->cycle_done) return;
     __shared__ double sh[BLOCK / WAVE];
     src += bi * bt.vec;
-    V += bi * bt.basis;
     partial += bi * bt.part;
     const double div = use_beta ? ctl->beta : ctl->hnext;
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * BLOCK) {
         const KT t = (KT)((double)src[i] / div);
-        V[i * MP + col] = t;
         vcur[i * bt.vstep + bi] = t;
         s += (double)t * (double)t;
     }
@@ -242,7 +239,8 @@ __global__ __launch_bounds__(BLOCK) void k_fin_tau(int nblk, const double *parti
 
 // ---------------------------------------------------------------------------
 // Gram-Schmidt passes over the interleaved basis (8 lanes per row, lane q
-// owns entries k = 4 (q + 8 u) + e).  MODE 0: dots V_j^T w and ||w||^2.
+// owns entries k = 4 (q + 8 u) + e).  MODE 0: dots V_j^T w and ||w||^2;
+// column j (v_j) is taken from vcur and stored into the basis here.
 // MODE 1: w -= V_j hprev, then dots.  MODE 2: w -= V_j hprev, then ||w||^2.
 // Entries k > j are masked by selection (they may hold an older cycle).
 // ---------------------------------------------------------------------------
@@ -262,15 +260,17 @@ template <> struct Quad<double> {
 };
 
 template <typename KT, int MP, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, const KT *__restrict__ V,
+__global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__restrict__ V,
                                                int j, KT *__restrict__ w,
                                                const double *__restrict__ hprev,
                                                double *__restrict__ partial, int pstride,
-                                               const Ctl *ctl, Bat bt) {
+                                               const Ctl *ctl, Bat bt,
+                                               const KT *__restrict__ vcur) {
     ctl += blockIdx.y;
     if (ctl->cycle_done) return;
     V += blockIdx.y * bt.basis;
     w += blockIdx.y * bt.vec;
+    if (MODE == 0) vcur += blockIdx.y;
     if (hprev) hprev += blockIdx.y * bt.small;
     partial += blockIdx.y * bt.part;
     constexpr int NU = MP / 32, NA = 4 * NU;
@@ -288,9 +288,11 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, const KT 
     // every row of the block in one round of loads (rpb = RPP * RU)
     constexpr int RU0 = (sizeof(KT) == 4 ? 16 : 8) * 32 / MP;
     constexpr int RU = RU0 < 2 ? 2 : RU0;
+    // the lane owning column j (MODE 0 stores it)
+    const bool owner_j = q == ((j >> 2) & 7);
     for (int64_t ib = i0 + g; ib < i1; ib += (int64_t)RPP * RU) {
         KT v[RU][NA];
-        KT wold[RU];
+        KT wold[RU], vj[RU];
 #pragma unroll
         for (int ru = 0; ru < RU; ++ru) {
             const int64_t i = ib + (int64_t)ru * RPP;
@@ -306,11 +308,18 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, const KT 
                 }
             }
             wold[ru] = w[ic];
+            if (MODE == 0) vj[ru] = vcur[ic * bt.vstep];
         }
 #pragma unroll
         for (int ru = 0; ru < RU; ++ru) {
             const int64_t i = ib + (int64_t)ru * RPP;
             const bool ok = i < i1;
+            if (MODE == 0) {
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    if (4 * (q + 8 * (a / 4)) + a % 4 == j) v[ru][a] = vj[ru];
+                if (ok && owner_j) V[i * MP + j] = vj[ru];
+            }
             double vv[NA];
 #pragma unroll
             for (int a = 0; a < NA; ++a) {
@@ -379,13 +388,11 @@ __global__ __launch_bounds__(BLOCK) void k_fin_dots(int nblk, int j, const doubl
     if (ctl->cycle_done) return;
     partial += blockIdx.y * bt.part;
     hout += blockIdx.y * bt.small;
-    __shared__ double res[MAXCOL];
-    reduce_columns(nblk, j + 1, partial, pstride, res);
+    __shared__ double res[MAXCOL + 1];
+    // MODE 0 also sums the norm slot (last column of a partial row)
+    reduce_columns(nblk, j + 1, partial, pstride, res, MODE == 0 ? pstride - 1 : -1);
     for (int k = threadIdx.x; k <= j; k += BLOCK) hout[k] = res[k];
-    if (MODE == 0) {
-        reduce_columns(nblk, 1, partial + (pstride - 1), pstride, res);
-        if (threadIdx.x == 0) ctl->wnorm0 = sqrt(res[0]);
-    }
+    if (MODE == 0 && threadIdx.x == 0) ctl->wnorm0 = sqrt(res[j + 1]);
 }
 
 // h_{j+1,j} = ||w||, column j of H-bar = h1 + h2, Givens rotation, residual
@@ -664,8 +671,8 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     // not needed without a network
     const bool tau_in_encoder = model && c->prec != GNP_F64;
     const bool tau_kernel = model && !tau_in_encoder;
-    hipLaunchKernelGGL((k_normalize<KT, double, MP>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, V, 0,
-                       vcur, c->partial, c->ctl, 1, Bat{});
+    hipLaunchKernelGGL((k_normalize<KT, double>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, vcur,
+                       c->partial, c->ctl, 1, Bat{});
     if (tau_kernel)
         hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
                            c->ctl, Bat{}, (int *)nullptr);
@@ -675,25 +682,25 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
             GNP_TRY(forward_launch(model, c->prec, vcur, zj, 1, c->tau, c->act[0], c->act[1], skip,
                                    st, nullptr, tau_in_encoder ? c->partial : nullptr, sg));
         spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st);
-        hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
-                           (const KT *)V, j, w, (const double *)nullptr, c->partial, pstride,
-                           (const Ctl *)c->ctl, Bat{});
+        hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
+                           (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
+                           Bat{}, (const KT *)vcur);
         hipLaunchKernelGGL(k_fin_dots<0>, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, Bat{});
-        hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
-                           (const KT *)V, j, w, (const double *)c->h1, c->partial, pstride,
-                           (const Ctl *)c->ctl, Bat{});
+        hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
+                           (const double *)c->h1, c->partial, pstride, (const Ctl *)c->ctl,
+                           Bat{}, (const KT *)nullptr);
         hipLaunchKernelGGL(k_fin_dots<1>, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h2, c->ctl, Bat{});
-        hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb,
-                           (const KT *)V, j, w, (const double *)c->h2, c->partial, pstride,
-                           (const Ctl *)c->ctl, Bat{});
+        hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
+                           (const double *)c->h2, c->partial, pstride, (const Ctl *)c->ctl,
+                           Bat{}, (const KT *)nullptr);
         hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, (const double *)c->h1,
                            (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
                            c->hist, Bat{});
-        hipLaunchKernelGGL((k_normalize<KT, KT, MP>), dim3(sg), dim3(BLOCK), 0, st, n,
-                           (const KT *)w, V, j + 1, vcur, c->partial, c->ctl, 0, Bat{});
+        hipLaunchKernelGGL((k_normalize<KT, KT>), dim3(sg), dim3(BLOCK), 0, st, n,
+                           (const KT *)w, vcur, c->partial, c->ctl, 0, Bat{});
         if (tau_kernel)
             hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
                                c->ctl, Bat{}, (int *)nullptr);
@@ -905,8 +912,8 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
     const int gcgs = (int)((n + rpb - 1) / rpb);
     const int pstride = MP + 1;
     float *V = c->V, *w = c->w;
-    hipLaunchKernelGGL((k_normalize<float, double, MP>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
-                       (const double *)c->r, V, 0, c->vpk, c->partial, (const Ctl *)c->ctl, 1, bt);
+    hipLaunchKernelGGL((k_normalize<float, double>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
+                       (const double *)c->r, c->vpk, c->partial, (const Ctl *)c->ctl, 1, bt);
     hipLaunchKernelGGL(k_fin_tau, dim3(1, nb), dim3(BLOCK), 0, st, sg, (const double *)c->partial,
                        n, c->tau, (const Ctl *)c->ctl, bt, c->all_done);
     for (int j = 0; j < nsteps; ++j) {
@@ -916,26 +923,25 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
         spmv_launch<float, float, float>(n, s->rp, s->ci, s->val32, zj, w, nullptr,
                                          &c->ctl->cycle_done, s->nnz, st, nb, nb, n,
                                          (int)(sizeof(Ctl) / sizeof(int)));
-        hipLaunchKernelGGL((k_cgs<float, MP, 0>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb,
-                           (const float *)V, j, w, (const double *)nullptr, c->partial, pstride,
-                           (const Ctl *)c->ctl, bt);
+        hipLaunchKernelGGL((k_cgs<float, MP, 0>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
+                           w, (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
+                           bt, (const float *)c->vpk);
         hipLaunchKernelGGL(k_fin_dots<0>, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, bt);
-        hipLaunchKernelGGL((k_cgs<float, MP, 1>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb,
-                           (const float *)V, j, w, (const double *)c->h1, c->partial, pstride,
-                           (const Ctl *)c->ctl, bt);
+        hipLaunchKernelGGL((k_cgs<float, MP, 1>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
+                           w, (const double *)c->h1, c->partial, pstride, (const Ctl *)c->ctl,
+                           bt, (const float *)nullptr);
         hipLaunchKernelGGL(k_fin_dots<1>, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h2, c->ctl, bt);
-        hipLaunchKernelGGL((k_cgs<float, MP, 2>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb,
-                           (const float *)V, j, w, (const double *)c->h2, c->partial, pstride,
-                           (const Ctl *)c->ctl, bt);
+        hipLaunchKernelGGL((k_cgs<float, MP, 2>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
+                           w, (const double *)c->h2, c->partial, pstride, (const Ctl *)c->ctl,
+                           bt, (const float *)nullptr);
         hipLaunchKernelGGL(k_fin_givens, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, (const double *)c->h1,
                            (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
                            c->hist, bt);
-        hipLaunchKernelGGL((k_normalize<float, float, MP>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
-                           (const float *)w, V, j + 1, c->vpk, c->partial, (const Ctl *)c->ctl, 0,
-                           bt);
+        hipLaunchKernelGGL((k_normalize<float, float>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
+                           (const float *)w, c->vpk, c->partial, (const Ctl *)c->ctl, 0, bt);
         hipLaunchKernelGGL(k_fin_tau, dim3(1, nb), dim3(BLOCK), 0, st, sg,
                            (const double *)c->partial, n, c->tau, (const Ctl *)c->ctl, bt,
                            c->all_done);
