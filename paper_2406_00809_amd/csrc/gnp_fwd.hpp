@@ -678,13 +678,16 @@ __device__ __forceinline__ void layer_tiles(
 // previous tile.  All loads are unconditional (clamped addresses, results
 // unused when out of range), so the compiler can count them.  The rowptr
 // slice stays in registers (cross-lane reads), the MFMA weight fragments are
-// staged in LDS once per block.
+// staged in LDS once per block.  With DEC the layer is the last one and the
+// decoder follows on the tile: z = tau_2 (ReLU(Y W3 + c3) W4 + c4), Eq. (6).
 // ---------------------------------------------------------------------------
-template <int D, int H>
+template <int D, int H, bool DEC, typename ZT>
 __device__ __forceinline__ void layer_tiles_bf16(
     int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const uint16_t *__restrict__ ahat, const uint16_t *__restrict__ X, uint16_t *__restrict__ Y,
-    const void *__restrict__ wcat, const int *__restrict__ skip) {
+    const void *__restrict__ wcat, const void *__restrict__ w3, const float *__restrict__ vec,
+    int64_t oc3, int64_t oW4, int64_t oc4, const double *__restrict__ tau, ZT *__restrict__ z,
+    const int *__restrict__ skip) {
     if (skip && *skip) return;
     using G = uint16_t;
     constexpr int LD = 2 * D + lds_pad<G>();
@@ -692,16 +695,28 @@ __device__ __forceinline__ void layer_tiles_bf16(
     constexpr int KB = 2 * D / 32, NT = D / 16;  // MFMA k-blocks and n-tiles
     constexpr int CB = (D / 4) * (int)sizeof(G);  // bytes per lane per row
     constexpr int NB = 8;                         // neighbour loads per batch
+    constexpr int KP = ((D + 31) / 32) * 32;      // decoder K, zero-padded
+    constexpr int NW3 = DEC ? (KP / 32) * (H / 16) * WAVE : 1;  // W3 fragments (x 8 bf16)
     __shared__ __attribute__((aligned(16))) G As[BLOCK / WAVE][16][LD];
     __shared__ uint32_t sCo[BLOCK / WAVE][CAP];  // byte offset of row (column, rhs 0) in X
     __shared__ uint16_t sVa[BLOCK / WAVE][CAP];
     __shared__ __attribute__((aligned(16))) uint16_t sW[KB * NT * WAVE * 8];
+    __shared__ __attribute__((aligned(16))) uint16_t sW3[NW3 * 8];
+    __shared__ __attribute__((aligned(16))) float sC3[DEC ? H : 4], sW4[DEC ? H : 4];
     const int lane = threadIdx.x % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(wcat);
         for (int e = threadIdx.x; e < KB * NT * WAVE; e += BLOCK)
             reinterpret_cast<uint4 *>(sW)[e] = src[e];
+        if constexpr (DEC) {
+            const uint4 *src3 = reinterpret_cast<const uint4 *>(w3);
+            for (int e = threadIdx.x; e < NW3; e += BLOCK) reinterpret_cast<uint4 *>(sW3)[e] = src3[e];
+            for (int e = threadIdx.x; e < H; e += BLOCK) {
+                sC3[e] = vec[oc3 + e];
+                sW4[e] = vec[oW4 + e];
+            }
+        }
         __syncthreads();
     }
     const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv);
@@ -862,11 +877,56 @@ __device__ __forceinline__ void layer_tiles_bf16(
                         load_bf16x8(sW + ((kb * NT + nt) * WAVE + lane) * 8), xf, o[nt], 0, 0, 0);
             }
             const int64_t r = r0 + lane % 16;
-            if (r < rows) {
+            if constexpr (!DEC) {
+                if (r < rows) {
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    *reinterpret_cast<uint2 *>(Y + r * D + nt * 16 + 4 * (lane / 16)) =
-                        make_uint2(relu_pk_bf16(o[nt][0], o[nt][1]), relu_pk_bf16(o[nt][2], o[nt][3]));
+                    for (int nt = 0; nt < NT; ++nt)
+                        *reinterpret_cast<uint2 *>(Y + r * D + nt * 16 + 4 * (lane / 16)) =
+                            make_uint2(relu_pk_bf16(o[nt][0], o[nt][1]),
+                                       relu_pk_bf16(o[nt][2], o[nt][3]));
+                }
+            } else {
+                // ---- decoder: Y (bf16, K zero-padded to KP) to LDS, then
+                // hidden^T = W3^T Y^T on MFMA, then ReLU(. + c3) W4 per row
+                wave_lds_sync();  // every lane has read its tile fragments
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int f = nt * 16 + 4 * (lane / 16);
+                    *reinterpret_cast<uint2 *>(&As[wv][lane % 16][f]) = make_uint2(
+                        relu_pk_bf16(o[nt][0], o[nt][1]), relu_pk_bf16(o[nt][2], o[nt][3]));
+                    if constexpr (KP > D)
+                        *reinterpret_cast<uint2 *>(&As[wv][lane % 16][D + f]) = make_uint2(0u, 0u);
+                }
+                wave_lds_sync();
+                f32x4 hacc[H / 16];
+#pragma unroll
+                for (int nt = 0; nt < H / 16; ++nt) hacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KP / 32; ++kb) {
+                    const bf16x8 yf = load_bf16x8(&As[wv][lane % 16][kb * 32 + 8 * (lane / 16)]);
+#pragma unroll
+                    for (int nt = 0; nt < H / 16; ++nt)
+                        hacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            load_bf16x8(sW3 + ((kb * (H / 16) + nt) * WAVE + lane) * 8), yf,
+                            hacc[nt], 0, 0, 0);
+                }
+                // lane holds hidden units nt*16 + 4 (l/16) + j of row l % 16
+                float part = 0.f;
+#pragma unroll
+                for (int nt = 0; nt < H / 16; ++nt) {
+                    const int k0 = nt * 16 + 4 * (lane / 16);
+                    const float4 c3 = *reinterpret_cast<const float4 *>(&sC3[k0]);
+                    const float4 w4 = *reinterpret_cast<const float4 *>(&sW4[k0]);
+                    part += fmaxf(hacc[nt][0] + c3.x, 0.f) * w4.x;
+                    part += fmaxf(hacc[nt][1] + c3.y, 0.f) * w4.y;
+                    part += fmaxf(hacc[nt][2] + c3.z, 0.f) * w4.z;
+                    part += fmaxf(hacc[nt][3] + c3.w, 0.f) * w4.w;
+                }
+                part += __shfl_xor(part, 16, WAVE);
+                part += __shfl_xor(part, 32, WAVE);
+                if (lane < 16 && r < rows)
+                    z[r] = (ZT)(tau[3 * ((uint32_t)r % (uint32_t)B) + 2] *
+                                (double)(part + vec[oc4]));
             }
         }
         // ---- the next tile's slice to LDS (this tile's gather has read its
@@ -897,23 +957,21 @@ __global__ __launch_bounds__(BLOCK) void k_layer(GNP_LAYER_PARAMS) {
     layer_tiles<G, D, H, DEC, ZT>(GNP_LAYER_ARGS);
 }
 
-// The same kernel held to 128 registers (4 wavefronts per SIMD): more
-// wavefronts in flight hide more of the gather latency.  Used for the
-// bfloat16 layers without the fused decoder, which fit without spilling.
-template <typename G, int D, int H, typename ZT>
+// The bfloat16 layers (and the last one with the decoder), held to 128
+// registers: at least 4 wavefronts per SIMD.
+template <typename G, int D, int H, bool DEC, typename ZT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_layer_w4(
     GNP_LAYER_PARAMS) {
-    if constexpr (sizeof(G) == 2)
-        layer_tiles_bf16<D, H>(rows, B, rp, ci, ahat, X, Y, wcat, skip);
-    else
-        layer_tiles<G, D, H, false, ZT>(GNP_LAYER_ARGS);
+    static_assert(sizeof(G) == 2, "bfloat16 layer");
+    layer_tiles_bf16<D, H, DEC, ZT>(rows, B, rp, ci, ahat, X, Y, wcat, w3, vec, oc3, oW4, oc4, tau,
+                                    z, skip);
 }
 #undef GNP_LAYER_PARAMS
 #undef GNP_LAYER_ARGS
 
 // The layer kernel to launch for a configuration.
 template <typename G, int D, int H, bool DEC, typename ZT> inline auto layer_kernel() {
-    if constexpr (!DEC && sizeof(G) == 2) return &k_layer_w4<G, D, H, ZT>;
+    if constexpr (sizeof(G) == 2) return &k_layer_w4<G, D, H, DEC, ZT>;
     else return &k_layer<G, D, H, DEC, ZT>;
 }
 
