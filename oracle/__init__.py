@@ -65,6 +65,7 @@ def lib():
         L.or_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64]
         L.or_normal.restype = C.c_double
         L.or_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, F64P]
+        L.or_normals_stream.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, F64P]
         L.or_train.argtypes = [C.c_int64, I32P, I32P, F64P, F64P, C.c_int, C.c_int, C.c_int,
                                F64P, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_uint64, C.c_void_p, C.c_void_p,
@@ -180,6 +181,59 @@ def normals(seed, step, count):
     out = np.empty(count)
     lib().or_normals(seed, step, count, out)
     return out
+
+
+def normals_stream(seed, step, stream, count):
+    """Normals of Philox stream `stream` (counter word 3): 0 = x ~ N(0, I)
+    batches, 1 = the coefficients eps of Eq. (3), 2 = the Arnoldi start."""
+    out = np.empty(count)
+    lib().or_normals_stream(seed, step, stream, count, out)
+    return out
+
+
+# --- training-pair sampler (Sec. 2.2, Eqs. (2)-(3)) ------------------------
+
+SV_DROP = 1e-12  # singular values below SV_DROP * s_max are treated as zero
+
+
+def arnoldi_sampler(S: System, m, seed):
+    """m steps of the Arnoldi process without a preconditioner (Eq. (2)),
+    started from xi / ||xi||, xi ~ N(0, I) (stream 2, step 0); then the thin
+    SVD Hbar = W S Z^T (numpy's LAPACK routine as the step), written in a
+    canonical form: singular values in decreasing order, each column of Z
+    with its entry of largest magnitude positive (W's column flipped with
+    it).  Returns V (n x (k+1)), Hbar ((k+1) x k), W, s, Z and
+    G = Z S^+ (zero columns for dropped singular values), k = steps done
+    (fewer than m after a breakdown)."""
+    xi = normals_stream(seed, 0, 2, S.n)
+    r = fgmres(S, xi, m, 1e-300, m, M="identity", ortho=CGS2, dump=True)
+    k = r["k"]
+    V = r["V"][:k + 1].T.copy()
+    Hbar = r["H"][:k + 1, :k].copy()
+    W, sv, Zt = np.linalg.svd(Hbar, full_matrices=False)
+    Z = Zt.T.copy()
+    for c in range(k):
+        i = int(np.argmax(np.abs(Z[:, c])))
+        if Z[i, c] < 0:
+            Z[:, c] = -Z[:, c]
+            W[:, c] = -W[:, c]
+    keep = sv > SV_DROP * sv[0]
+    G = np.where(keep[None, :], Z / np.where(keep, sv, 1.0)[None, :], 0.0)
+    return dict(V=V, Hbar=Hbar, W=W, s=sv, Z=Z, G=G, k=k, seed=seed)
+
+
+def sampler_eps(samp, step, count):
+    """eps_k ~ N(0, I_k) for k = 0..count-1 of training step `step` (stream
+    1, element e = k * steps + j), as an array [count][steps]."""
+    k = samp["k"]
+    return normals_stream(samp["seed"], step, 1, count * k).reshape(count, k)
+
+
+def sampler_draw(samp, step, count):
+    """x = V_m Z S^{-1} eps (Eq. (3)) for `count` draws: [n][count]."""
+    k = samp["k"]
+    eps = sampler_eps(samp, step, count)
+    return samp["V"][:, :k] @ (samp["G"] @ eps.T)
 
 
 def train(S: System, L, d, h, theta0, steps, B, lr=1e-3, seed=2, x_fixed=None,

@@ -458,12 +458,14 @@ OR_API void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint3
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Standard normal number e of training step `step` for seed `seed`:
- * counter = (e_lo, e_hi, step, 0), key = (seed_lo, seed_hi); two 53-bit
- * uniforms in (0,1) from the four output words; z = sqrt(-2 ln u1) cos(2 pi u2). */
-OR_API double or_normal(uint64_t seed, uint32_t step, uint64_t e)
+/* Standard normal number e of stream `stream`, training step `step`, for
+ * seed `seed`: counter = (e_lo, e_hi, step, stream), key = (seed_lo,
+ * seed_hi); two 53-bit uniforms in (0,1) from the four output words;
+ * z = sqrt(-2 ln u1) cos(2 pi u2).  Stream 0: the x ~ N(0, I) training
+ * batches; 1: the coefficients eps of Eq. (3); 2: the Arnoldi start vector. */
+OR_API double or_normal_stream(uint64_t seed, uint32_t step, uint32_t stream, uint64_t e)
 {
-    uint32_t ctr[4] = {(uint32_t)e, (uint32_t)(e >> 32), step, 0u};
+    uint32_t ctr[4] = {(uint32_t)e, (uint32_t)(e >> 32), step, stream};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t o[4];
     or_philox4x32_10(ctr, key, o);
@@ -473,10 +475,22 @@ OR_API double or_normal(uint64_t seed, uint32_t step, uint64_t e)
     return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
 }
 
+OR_API double or_normal(uint64_t seed, uint32_t step, uint64_t e)
+{
+    return or_normal_stream(seed, step, 0u, e);
+}
+
 OR_API void or_normals(uint64_t seed, uint32_t step, int64_t count, double *out)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < count; ++e) out[e] = or_normal(seed, step, (uint64_t)e);
+}
+
+OR_API void or_normals_stream(uint64_t seed, uint32_t step, uint32_t stream, int64_t count,
+                              double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < count; ++e) out[e] = or_normal_stream(seed, step, stream, (uint64_t)e);
 }
 
 /* ------------------------------------------------------------------------ */
