@@ -53,6 +53,7 @@ typedef enum { GNP_F64 = 0, GNP_F32 = 1, GNP_BF16 = 2 } gnp_precision;
 
 typedef struct gnp_system gnp_system;
 typedef struct gnp_model gnp_model;
+typedef struct gnp_sampler gnp_sampler;
 
 /* Message describing the last failure on the calling thread. */
 GNP_API const char *gnp_last_error(void);
@@ -213,15 +214,23 @@ typedef struct {
     double lr;           /* Adam learning rate (the paper uses 1e-3) */
     double beta1, beta2; /* Adam moment decay rates (0.9, 0.999) */
     double eps;          /* Adam epsilon (1e-8) */
-    uint64_t seed;       /* seed of the x ~ N(0, I) sampler */
+    uint64_t seed;       /* seed of the samplers */
     gnp_precision prec;  /* GNP_F32 or GNP_F64 */
+    int sampler_m;       /* 0: every x ~ N(0, I); 1..64: Arnoldi steps of the
+                            Eq. (3) sampler (the paper uses 40) */
+    int sampler_count;   /* with sampler_m > 0: the first sampler_count columns
+                            of every batch are drawn from Eq. (3), the others
+                            from N(0, I) (the paper: 8 of 16); 0..batch */
 } gnp_train_opts;
 
 /* Train the network on streaming pairs (b = A x, x): every step draws
  * x ~ N(0, I) ([n][batch]) with a counter-based Philox4x32-10 generator
  * (counter = (element index low, high, step, 0), key = seed) and the
  * Box-Muller transform, unless x_fixed_dev (float64 device, [n][batch]) is
- * given, in which case that batch is used at every step.  Loss: mean over the
+ * given, in which case that batch is used at every step.  With
+ * opts->sampler_m > 0 a sampler as gnp_sampler_create(system, sampler_m,
+ * seed) is built first and columns 0..sampler_count-1 of every drawn batch
+ * are replaced by its draws for that step (gnp_sampler_draw).  Loss: mean over the
  * n*batch entries of |A M(b) - b| (the l1 residual of Sec. 3); gradient by the
  * hand-written backward; update: bias-corrected Adam on float64 master
  * weights.  At the end the model holds the weights of the step with the
@@ -233,6 +242,39 @@ typedef struct {
 GNP_API gnp_status gnp_train(gnp_model *model, const gnp_train_opts *opts,
                              const double *x_fixed_dev, double *loss_hist, int *best_step,
                              void *hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Training-pair sampler (Sec. 2.2, Eqs. (2)-(3))                            */
+/* ------------------------------------------------------------------------ */
+
+/* Run m steps (1..64, below n) of the Arnoldi process without a
+ * preconditioner, A V_m = V_{m+1} Hbar_m (Eq. (2)), in FP64 with CGS2,
+ * from xi / ||xi||, xi ~ N(0, I) drawn from the Philox generator with
+ * counter (element low, high, 0, 2) and key seed; then the thin SVD
+ * Hbar_m = W S Z^T on the device (one-sided Jacobi, FP64) in canonical form
+ * (singular values decreasing, the entry of largest magnitude of each
+ * column of Z positive) and G = Z S^+ (singular values <= 1e-12 s_max
+ * dropped).  A breakdown ends the process early: k < m steps are used.
+ * max_count: most draws per gnp_sampler_draw call (1..256).  The sampler
+ * keeps V_k and G on the device (n * pitch + ... doubles) and refers to
+ * the system, which must outlive it.  Synchronises the stream.
+ * Errors: GNP_EINVAL for bad arguments; GNP_ENUMERIC for a non-finite
+ * Arnoldi process; GNP_ENOMEM. */
+GNP_API gnp_status gnp_sampler_create(gnp_system *sys, int m, uint64_t seed, int max_count,
+                                      void *hip_stream, gnp_sampler **out);
+
+/* Host copies of what the sampler built (each optional): *k = steps used,
+ * hbar = Hbar_k ((k+1) x k, row-major), sv = the k singular values
+ * (decreasing), G = Z S^+ (k x k, row-major).  Synchronous. */
+GNP_API gnp_status gnp_sampler_info(const gnp_sampler *s, int *k, double *hbar, double *sv,
+                                    double *G);
+
+/* x_dev (float64 device, [n][count]): column d = V_k G eps_d, the draw of
+ * Eq. (3), with eps_d[j] the Philox normal of counter (d k + j, 0, step, 1)
+ * and key seed.  count in 1..max_count.  Stream-ordered. */
+GNP_API gnp_status gnp_sampler_draw(gnp_sampler *s, uint32_t step, int count, double *x_dev,
+                                    void *hip_stream);
+GNP_API void gnp_sampler_destroy(gnp_sampler *s);
 
 /* Loss and gradient at the current weights for one batch b_dev (float64
  * device, [n][nrhs]): *loss = mean |A M(b) - b|, grad (host, optional,

@@ -27,7 +27,8 @@ VP, I32P, F64P = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)
 class TrainOpts(C.Structure):
     _fields_ = [("steps", C.c_int), ("batch", C.c_int), ("lr", C.c_double),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
-                ("seed", C.c_uint64), ("prec", C.c_int)]
+                ("seed", C.c_uint64), ("prec", C.c_int), ("sampler_m", C.c_int),
+                ("sampler_count", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -92,6 +93,10 @@ SIGNATURES = {
     "gnp_server_drain": (C.c_int, [VP, C.c_double]),
     "gnp_server_get_stats": (C.c_int, [VP, C.POINTER(ServerStats)]),
     "gnp_server_destroy": (None, [VP]),
+    "gnp_sampler_create": (C.c_int, [VP, C.c_int, C.c_uint64, C.c_int, VP, C.POINTER(VP)]),
+    "gnp_sampler_info": (C.c_int, [VP, C.POINTER(C.c_int), VP, VP, VP]),
+    "gnp_sampler_draw": (C.c_int, [VP, C.c_uint32, C.c_int, VP, VP]),
+    "gnp_sampler_destroy": (None, [VP]),
 }
 
 _lib = None

@@ -163,10 +163,14 @@ class Model:
 
     def train(self, steps: int, batch: int, lr: float = 1e-3, seed: int = 2, prec="f32",
               x_fixed: torch.Tensor | None = None, betas=(0.9, 0.999), eps: float = 1e-8,
-              stream=None):
-        """gnp_train: returns (loss history ndarray, best step)."""
+              sampler_m: int = 0, sampler_count: int | None = None, stream=None):
+        """gnp_train: returns (loss history ndarray, best step).  sampler_m > 0
+        draws the first sampler_count (default batch // 2) columns of every
+        batch from the Arnoldi sampler of Eq. (3) with sampler_m steps."""
+        if sampler_count is None:
+            sampler_count = batch // 2 if sampler_m > 0 else 0
         o = TrainOpts(int(steps), int(batch), float(lr), float(betas[0]), float(betas[1]),
-                      float(eps), int(seed), PREC[prec])
+                      float(eps), int(seed), PREC[prec], int(sampler_m), int(sampler_count))
         hist = np.empty(steps)
         best = C.c_int(-1)
         xf = None
@@ -243,6 +247,51 @@ def fgmres_solve_batch(system: System, B: torch.Tensor, model: Model, X: torch.T
         _dev_ptr(X, torch.float64, nrhs * system.n, "X"), int(nrhs), int(m), float(rtol),
         int(maxiters), PREC[prec], C.cast(infos, C.c_void_p), _stream(stream)))
     return X, [infos[k].as_dict() for k in range(nrhs)]
+
+
+class Sampler:
+    """Training-pair sampler of Eqs. (2)-(3) (gnp_sampler_*): m Arnoldi steps
+    of the system's matrix without a preconditioner, SVD of Hbar; draw()
+    returns x = V_m Z S^+ eps ([n, count] float64, device)."""
+
+    def __init__(self, system: System, m: int = 40, seed: int = 2, max_count: int = 256,
+                 stream=None):
+        h = C.c_void_p()
+        check(_lib.load().gnp_sampler_create(system.handle, int(m), int(seed), int(max_count),
+                                             _stream(stream), C.byref(h)))
+        self._h = h
+        self.system = system
+
+    def info(self):
+        """(k, Hbar [(k+1) x k], singular values [k], G [k x k]) as numpy arrays."""
+        k = C.c_int()
+        check(_lib.load().gnp_sampler_info(self._h, C.byref(k), None, None, None))
+        k = k.value
+        hb = np.empty((k + 1, k))
+        sv = np.empty(k)
+        G = np.empty((k, k))
+        check(_lib.load().gnp_sampler_info(self._h, None, hb.ctypes.data_as(C.c_void_p),
+                                           sv.ctypes.data_as(C.c_void_p),
+                                           G.ctypes.data_as(C.c_void_p)))
+        return k, hb, sv, G
+
+    def draw(self, step: int, count: int, stream=None) -> torch.Tensor:
+        x = torch.empty((self.system.n, count), dtype=torch.float64, device="cuda")
+        check(_lib.load().gnp_sampler_draw(self._h, int(step), int(count),
+                                           _dev_ptr(x, torch.float64, self.system.n * count, "x"),
+                                           _stream(stream)))
+        return x
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().gnp_sampler_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

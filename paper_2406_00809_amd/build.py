@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libgnp.so")
-SOURCES = ["system.hip", "gnp.hip", "solver.hip", "train.hip", "server.hip"]
+SOURCES = ["system.hip", "gnp.hip", "solver.hip", "train.hip", "server.hip", "sampler.hip"]
 ARCH = os.environ.get("GNP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -21,6 +21,8 @@
 #include "bwd_mfma.hpp"
 #include "gnp_fwd.hpp"
 #include "model.hpp"
+#include "philox.hpp"
+#include "sampler.hpp"
 
 namespace gnp {
 
@@ -28,33 +30,13 @@ constexpr int TB = 64;       // rows per block tile
 constexpr int NBG_MAX = 1024;  // blocks of the gradient kernels
 
 // ---------------------------------------------------------------------------
-// sampler: Philox4x32-10 (Salmon et al., SC'11) + Box-Muller (1958)
+// x ~ N(0, I) batches: stream 0 of the counter-based generator (philox.hpp)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-        c[1] = (uint32_t)p1;
-        c[3] = (uint32_t)p0;
-        c[0] = n0;
-        c[2] = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
 template <typename T>
 __global__ void k_normals(int64_t count, uint64_t seed, uint32_t step, T *__restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
-    uint32_t c[4] = {(uint32_t)e, (uint32_t)((uint64_t)e >> 32), step, 0u};
-    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double two53 = 9007199254740992.0;
-    const double u1 = ((double)((((uint64_t)(c[0] >> 5)) << 26) | (c[1] >> 6)) + 0.5) / two53;
-    const double u2 = ((double)((((uint64_t)(c[2] >> 5)) << 26) | (c[3] >> 6)) + 0.5) / two53;
-    out[e] = (T)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2));
+    out[e] = (T)normal_at(seed, step, 0u, (uint64_t)e);
 }
 
 template <typename S, typename T>
@@ -658,7 +640,7 @@ static void loss_dz(gnp_model *m, TrainCtx *c, const T *bin, const T *z, double 
 
 template <typename T, int D, int H>
 static gnp_status train_typed(gnp_model *m, TrainCtx *c, const gnp_train_opts *o,
-                              const double *x_fixed, hipStream_t st) {
+                              const double *x_fixed, gnp_sampler *samp, hipStream_t st) {
     gnp_system *s = m->sys;
     const int64_t rows = c->rows;
     const T *val = sizeof(T) == 8 ? (const T *)s->val64 : (const T *)s->val32;
@@ -672,9 +654,13 @@ static gnp_status train_typed(gnp_model *m, TrainCtx *c, const gnp_train_opts *o
     if (x_fixed)
         hipLaunchKernelGGL((k_convert<double, T>), dim3(ge), dim3(BLOCK), 0, st, rows, x_fixed, x);
     for (int t = 0; t < o->steps; ++t) {
-        if (!x_fixed)
+        if (!x_fixed) {
             hipLaunchKernelGGL((k_normals<T>), dim3(ge), dim3(BLOCK), 0, st, rows, o->seed,
                                (uint32_t)t, x);
+            if (samp)  // the first sampler_count columns from Eq. (3)
+                GNP_TRY(sampler_draw_launch<T>(samp, (uint32_t)t, o->sampler_count, c->nrhs, x,
+                                               st));
+        }
         hipLaunchKernelGGL((k_spmm_rhs<T>), dim3(ge), dim3(BLOCK), 0, st, s->n, c->nrhs, s->rp,
                            s->ci, val, (const T *)x, b);
         fwd_save<T, D, H>(m, c, b, z, st);
@@ -697,9 +683,9 @@ static gnp_status train_typed(gnp_model *m, TrainCtx *c, const gnp_train_opts *o
 
 template <int D, int H>
 static gnp_status train_dispatch(gnp_model *m, TrainCtx *c, const gnp_train_opts *o,
-                                 const double *x_fixed, hipStream_t st) {
-    if (o->prec == GNP_F64) return train_typed<double, D, H>(m, c, o, x_fixed, st);
-    return train_typed<float, D, H>(m, c, o, x_fixed, st);
+                                 const double *x_fixed, gnp_sampler *samp, hipStream_t st) {
+    if (o->prec == GNP_F64) return train_typed<double, D, H>(m, c, o, x_fixed, samp, st);
+    return train_typed<float, D, H>(m, c, o, x_fixed, samp, st);
 }
 
 template <typename T, int D, int H>
@@ -751,12 +737,23 @@ gnp_status gnp_train(gnp_model *m, const gnp_train_opts *o, const double *x_fixe
         !(o->beta2 >= 0.0 && o->beta2 < 1.0) || !(o->eps > 0.0))
         return fail(GNP_EINVAL, "bad Adam hyperparameters");
     GNP_TRY(check_train_prec(o->prec));
+    if (o->sampler_m < 0 || (o->sampler_m > 0 && (o->sampler_count < 0 ||
+                                                  o->sampler_count > o->batch)))
+        return fail(GNP_EINVAL, "sampler_m must be >= 0 and sampler_count in [0, batch]");
     hipStream_t st = (hipStream_t)hip_stream;
     TrainCtx *c = nullptr;
     GNP_TRY(train_ctx_get(m, o->prec, o->batch, o->steps, &c));
     c->have_fwd = 0;
-    if (m->d == 16) GNP_TRY((train_dispatch<16, 32>(m, c, o, x_fixed_dev, st)));
-    else GNP_TRY((train_dispatch<32, 64>(m, c, o, x_fixed_dev, st)));
+    // the sampler lives for this call; freeing its device memory waits for
+    // the kernels that still use it
+    struct SamplerGuard {
+        gnp_sampler *p = nullptr;
+        ~SamplerGuard() { sampler_destroy(p); }
+    } samp;
+    if (o->sampler_m > 0 && o->sampler_count > 0 && !x_fixed_dev)
+        GNP_TRY(sampler_create(m->sys, o->sampler_m, o->seed, o->batch, st, &samp.p));
+    if (m->d == 16) GNP_TRY((train_dispatch<16, 32>(m, c, o, x_fixed_dev, samp.p, st)));
+    else GNP_TRY((train_dispatch<32, 64>(m, c, o, x_fixed_dev, samp.p, st)));
     int flag = 0, bs = -1;
     GNP_HIP(hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     GNP_HIP(hipMemcpyAsync(&bs, c->best_step, sizeof(int), hipMemcpyDeviceToHost, st));

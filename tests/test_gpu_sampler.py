@@ -1,0 +1,116 @@
+"""Training-pair sampler (Sec. 2.2, Eqs. (2)-(3)) on the GPU against the oracle.
+
+The device runs m FP64 Arnoldi steps with the solver's CGS2 kernels, a
+one-sided Jacobi SVD of Hbar and the draws x = V_m Z S^+ eps; the oracle
+runs its own Algorithm 1 with M = I, LAPACK's SVD (numpy) and the same
+Philox streams.  Compared: the number of steps, Hbar, the singular values,
+G G^T = (Hbar^T Hbar)^+ (independent of the SVD's conventions) and, where the
+singular values are well separated (so that the canonical Z is well
+conditioned), G itself and the draws; then FP64 training with the sampler
+against an oracle training loop fed with the oracle's draws.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_00809_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    from paper_2406_00809_amd import api as A
+    return A
+
+
+def _nerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = {
+    "convdiff3d_12_m40": (lambda: I.convdiff3d(12), 40),
+    "powerlaw_3000_m40": (lambda: I.powerlaw_random(3000, seed_structure=13, seed_values=14), 40),
+    "laplace2d_30_m20": (lambda: I.laplace2d(30), 20),
+    "breakdown_laplace2d_3_m8": (lambda: I.laplace2d(3), 8),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_sampler_matches_oracle(api, case):
+    mk, m = CASES[case]
+    A = mk()
+    S = api.System(A)
+    ref = O.System(A)
+    seed = 5
+    sp = api.Sampler(S, m=m, seed=seed, max_count=8)
+    k, hb, sv, G = sp.info()
+    r = O.arnoldi_sampler(ref, m, seed)
+    print(case, "steps", k, "oracle", r["k"])
+    assert k == r["k"]
+    if case.startswith("breakdown"):
+        assert k < m
+    assert _nerr(hb, r["Hbar"]) < 1e-10
+    assert np.max(np.abs(sv - r["s"]) / r["s"][0]) < 1e-10
+    keep = r["s"] > 1e-12 * r["s"][0]
+    Gr = r["G"]
+    assert _nerr(G @ G.T, Gr @ Gr.T) < 1e-8
+    s = r["s"][keep]
+    gap = np.min(np.abs(np.diff(s)) / s[:-1]) if s.size > 1 else 1.0
+    print(f"smallest relative gap of the singular values {gap:.2e}")
+    if gap > 1e-4:
+        assert _nerr(G, Gr) < 1e-8
+        X = sp.draw(step=3, count=8).cpu().numpy()
+        Xr = O.sampler_draw(r, step=3, count=8)
+        for d in range(8):
+            assert _nerr(X[:, d], Xr[:, d]) < 1e-8, d
+    sp.close()
+
+
+def test_train_with_sampler_f64_matches_oracle(api):
+    """FP64 training, batch 4 with 2 columns from Eq. (3): loss history of 5
+    Adam steps against an oracle loop fed with the oracle's batches."""
+    import torch
+    A = I.laplace2d(16)
+    L, d, h, B, cnt, msamp, seed, steps = 2, 16, 32, 4, 2, 10, 7, 5
+    th0 = I.init_params(L, d, h, 3)
+    S = api.System(A)
+    M = api.Model(S, L, d, h, th0)
+    hist, best = M.train(steps, B, lr=1e-3, seed=seed, prec="f64", sampler_m=msamp,
+                         sampler_count=cnt)
+    ref = O.System(A)
+    samp = O.arnoldi_sampler(ref, msamp, seed)
+    theta = th0.copy()
+    mo, vo = np.zeros_like(theta), np.zeros_like(theta)
+    Ad = ref.A.to_scipy()
+    hr = []
+    for t in range(steps):
+        x = O.normals_stream(seed, t, 0, A.n * B).reshape(A.n, B)
+        x[:, :cnt] = O.sampler_draw(samp, t, cnt)
+        b = Ad @ x
+        loss, g = O.loss_grad(ref, L, d, h, theta, b)
+        hr.append(loss)
+        O.adam(theta, g, mo, vo, t + 1)
+    hr = np.asarray(hr)
+    print("gpu", hist, "oracle", hr)
+    np.testing.assert_allclose(hist, hr, rtol=1e-10)
+    assert best == int(np.argmin(hr))
+
+
+def test_sampler_errors(api):
+    A = I.laplace2d(6)
+    S = api.System(A)
+    from paper_2406_00809_amd._lib import GNPError
+    for kw in (dict(m=0), dict(m=65), dict(m=A.n), dict(max_count=0), dict(max_count=257)):
+        args = dict(m=5, seed=1, max_count=4)
+        args.update(kw)
+        with pytest.raises(GNPError):
+            api.Sampler(S, **args)
+    sp = api.Sampler(S, m=5, seed=1, max_count=4)
+    with pytest.raises(GNPError):
+        sp.draw(step=0, count=5)
+    M = api.Model(S, 2, 16, 32, I.init_params(2, 16, 32, 1))
+    with pytest.raises(GNPError):
+        M.train(2, 4, prec="f64", sampler_m=5, sampler_count=5)
