@@ -36,6 +36,36 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p))
 
 
+def spmv_bandwidth(S, dev, reps=50):
+    """FP32 SpMV of system S: warm (back-to-back launches on the same arrays)
+    and cold (a 512 MiB fill before every launch evicts L2 and the Infinity
+    Cache).  The cold time is (fill + SpMV) x reps minus fill x reps, both
+    timed with events on the launch stream, so launch gaps cancel."""
+    import torch
+    x = torch.randn(S.n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    nbytes = 8 * S.nnz + 4 * (S.n + 1) + 8 * S.n
+    warm_ms = S.time_spmv(x, y, prec="f32", reps=200)
+    flush = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+
+    def run(with_spmv):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for r in range(reps):
+            flush.fill_(float(r))
+            if with_spmv:
+                S.spmv(x, y, prec="f32")
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    run(True)
+    cold_ms = max(run(True) - run(False), 1e-6) / reps
+    return {"bytes": nbytes, "warm_us": 1e3 * warm_ms, "warm_GBps": nbytes / warm_ms / 1e6,
+            "cold_us": 1e3 * cold_ms, "cold_GBps": nbytes / cold_ms / 1e6}
+
+
 def cpu_baseline(A, th, arch, gpu_iters, sample_iters):
     """The oracle (FP64 C, OpenMP) on the same system, weights and b: the
     first `sample_iters` Arnoldi steps of the same FGMRES(30) solve, timed on
@@ -391,6 +421,14 @@ def main():
                                             "latency_p99_ms": 1e3 * st["latency_p99_s"]}
         log(f"32 rhs: float32 single solves {seq:.2f}/s ({conv32} converged), served "
             f"{args.prec} {served:.2f}/s ({convs} converged)")
+        # SpMV bandwidth, warm and cold, on this system and on the irregular
+        # power-law matrix (n = 2^20, 3..64 entries per row, mean 12)
+        extra["spmv_f32_bandwidth"] = spmv_bandwidth(S, dev)
+        A3 = I.powerlaw_random(1 << 20, seed_structure=3, seed_values=4)
+        S3 = api.System(A3)
+        extra["spmv_f32_bandwidth_powerlaw_2^20"] = {"nnz": A3.nnz, **spmv_bandwidth(S3, dev)}
+        S3.close()
+        log("spmv", extra["spmv_f32_bandwidth"], extra["spmv_f32_bandwidth_powerlaw_2^20"])
 
     # ---- dominant kernel: one Res-GCONV layer, same launch configuration
     lay_ms = M.time_layer(nrhs=1, prec=args.prec, reps=200)

@@ -196,20 +196,46 @@ def normals_stream(seed, step, stream, count):
 SV_DROP = 1e-12  # singular values below SV_DROP * s_max are treated as zero
 
 
+def arnoldi(S: System, v0, m):
+    """Eq. (2) written out: m steps of the Arnoldi process without a
+    preconditioner from v0 / ||v0||, A V_k = V_{k+1} Hbar_k, classical
+    Gram-Schmidt applied twice (Hbar's column = the sum of both passes), in
+    FP64.  A step whose new norm is <= 1e-14 ||A v_j|| is a breakdown: the
+    process ends there with k = j + 1 columns (that step's column kept, its
+    v_{k+1} left zero).  Returns V (n x (k+1)), Hbar ((k+1) x k), k."""
+    A = S.A.to_scipy()
+    n = S.n
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m))
+    V[:, 0] = v0 / np.linalg.norm(v0)
+    k = m
+    for j in range(m):
+        w = A @ V[:, j]
+        wn0 = np.linalg.norm(w)
+        Vj = V[:, :j + 1]
+        h1 = Vj.T @ w
+        w = w - Vj @ h1
+        h2 = Vj.T @ w
+        w = w - Vj @ h2
+        H[:j + 1, j] = h1 + h2
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] <= 1e-14 * wn0:
+            k = j + 1
+            break
+        V[:, j + 1] = w / H[j + 1, j]
+    return V[:, :k + 1].copy(), H[:k + 1, :k].copy(), k
+
+
 def arnoldi_sampler(S: System, m, seed):
-    """m steps of the Arnoldi process without a preconditioner (Eq. (2)),
-    started from xi / ||xi||, xi ~ N(0, I) (stream 2, step 0); then the thin
-    SVD Hbar = W S Z^T (numpy's LAPACK routine as the step), written in a
-    canonical form: singular values in decreasing order, each column of Z
-    with its entry of largest magnitude positive (W's column flipped with
-    it).  Returns V (n x (k+1)), Hbar ((k+1) x k), W, s, Z and
-    G = Z S^+ (zero columns for dropped singular values), k = steps done
-    (fewer than m after a breakdown)."""
+    """Training-pair sampler of Eqs. (2)-(3): Arnoldi (above) from
+    xi ~ N(0, I) (stream 2, step 0); then the thin SVD Hbar = W S Z^T (numpy's
+    LAPACK routine as the step), written in a canonical form: singular values
+    in decreasing order, each column of Z with its entry of largest magnitude
+    positive (W's column flipped with it).  Returns V (n x (k+1)), Hbar
+    ((k+1) x k), W, s, Z and G = Z S^+ (zero columns for dropped singular
+    values), k = steps done (fewer than m after a breakdown)."""
     xi = normals_stream(seed, 0, 2, S.n)
-    r = fgmres(S, xi, m, 1e-300, m, M="identity", ortho=CGS2, dump=True)
-    k = r["k"]
-    V = r["V"][:k + 1].T.copy()
-    Hbar = r["H"][:k + 1, :k].copy()
+    V, Hbar, k = arnoldi(S, xi, m)
     W, sv, Zt = np.linalg.svd(Hbar, full_matrices=False)
     Z = Zt.T.copy()
     for c in range(k):

@@ -52,12 +52,14 @@ __global__ void k_normals_stream(int64_t count, uint64_t seed, uint32_t step, ui
 }
 
 // Hbar (rows 0..k, columns 0..k-1 of the solver's row-major H0 with row
-// stride m) into U, column-major with k + 1 rows
+// stride m) into U, column-major with k + 1 rows.  Hbar is upper
+// Hessenberg: the solver writes rows r <= c + 1 of column c only, the rest
+// is zero by definition.
 __global__ void k_hbar_cols(int k, int m, const double *__restrict__ H0, double *__restrict__ U) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (k + 1) * k) return;
     const int c = e / (k + 1), r = e % (k + 1);
-    U[e] = H0[(int64_t)r * m + c];
+    U[e] = r <= c + 1 ? H0[(int64_t)r * m + c] : 0.0;
 }
 
 // One-sided Jacobi SVD of U ((rows) x k, column-major) on one workgroup:
@@ -303,8 +305,9 @@ gnp_status gnp_sampler_info(const gnp_sampler *sp, int *k, double *hbar, double 
     if (hbar) {
         std::vector<double> h0((size_t)(m + 1) * m);
         GNP_HIP(hipMemcpy(h0.data(), sp->ctx.H0, sizeof(double) * h0.size(), hipMemcpyDeviceToHost));
-        for (int r = 0; r <= kk; ++r)
-            for (int c = 0; c < kk; ++c) hbar[(size_t)r * kk + c] = h0[(size_t)r * m + c];
+        for (int r = 0; r <= kk; ++r)  // upper Hessenberg: zero below the subdiagonal
+            for (int c = 0; c < kk; ++c)
+                hbar[(size_t)r * kk + c] = r <= c + 1 ? h0[(size_t)r * m + c] : 0.0;
     }
     if (sv) GNP_HIP(hipMemcpy(sv, sp->sv, sizeof(double) * kk, hipMemcpyDeviceToHost));
     if (G) GNP_HIP(hipMemcpy(G, sp->G, sizeof(double) * kk * kk, hipMemcpyDeviceToHost));

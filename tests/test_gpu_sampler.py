@@ -52,11 +52,20 @@ def test_sampler_matches_oracle(api, case):
     assert k == r["k"]
     if case.startswith("breakdown"):
         assert k < m
-    assert _nerr(hb, r["Hbar"]) < 1e-10
-    assert np.max(np.abs(sv - r["s"]) / r["s"][0]) < 1e-10
-    keep = r["s"] > 1e-12 * r["s"][0]
     Gr = r["G"]
-    assert _nerr(G @ G.T, Gr @ Gr.T) < 1e-8
+    e_h = _nerr(hb, r["Hbar"])
+    e_s = np.max(np.abs(sv - r["s"]) / r["s"][0])
+    e_gg = _nerr(G @ G.T, Gr @ Gr.T)
+    print(f"Hbar {e_h:.2e}  singular values {e_s:.2e}  G G^T {e_gg:.2e}")
+    if e_h >= 1e-10:
+        d = np.abs(hb - r["Hbar"])
+        i, j = np.unravel_index(np.argmax(d), d.shape)
+        print("largest Hbar difference at", (i, j), hb[i, j], r["Hbar"][i, j])
+        print("gpu Hbar[:4,:4]", hb[:4, :4], "oracle", r["Hbar"][:4, :4], sep="\n")
+    assert e_h < 1e-10
+    assert e_s < 1e-10
+    keep = r["s"] > 1e-12 * r["s"][0]
+    assert e_gg < 1e-8
     s = r["s"][keep]
     gap = np.min(np.abs(np.diff(s)) / s[:-1]) if s.size > 1 else 1.0
     print(f"smallest relative gap of the singular values {gap:.2e}")
