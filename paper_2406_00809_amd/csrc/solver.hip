@@ -681,7 +681,8 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
         if (model)
             GNP_TRY(forward_launch(model, c->prec, vcur, zj, 1, c->tau, c->act[0], c->act[1], skip,
                                    st, nullptr, tau_in_encoder ? c->partial : nullptr, sg));
-        spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st);
+        spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st, 1, 1, 0, 0,
+                                s->max_row);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
                            Bat{}, (const KT *)vcur);
@@ -922,7 +923,7 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
                                c->all_done, st));
         spmv_launch<float, float, float>(n, s->rp, s->ci, s->val32, zj, w, nullptr,
                                          &c->ctl->cycle_done, s->nnz, st, nb, nb, n,
-                                         (int)(sizeof(Ctl) / sizeof(int)));
+                                         (int)(sizeof(Ctl) / sizeof(int)), s->max_row);
         hipLaunchKernelGGL((k_cgs<float, MP, 0>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
                            bt, (const float *)c->vpk);

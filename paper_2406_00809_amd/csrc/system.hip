@@ -381,11 +381,11 @@ gnp_status gnp_spmv(const gnp_system *sys, const void *x_dev, void *y_dev, gnp_p
     if (prec == GNP_F64)
         spmv_launch<double, double, double>(sys->n, sys->rp, sys->ci, sys->val64,
                                             (const double *)x_dev, (double *)y_dev, nullptr,
-                                            nullptr, sys->nnz, st);
+                                            nullptr, sys->nnz, st, 1, 1, 0, 0, sys->max_row);
     else
         spmv_launch<float, float, float>(sys->n, sys->rp, sys->ci, sys->val32,
                                          (const float *)x_dev, (float *)y_dev, nullptr,
-                                         nullptr, sys->nnz, st);
+                                         nullptr, sys->nnz, st, 1, 1, 0, 0, sys->max_row);
     GNP_HIP(hipGetLastError());
     return GNP_OK;
 }
