@@ -681,7 +681,7 @@ __device__ __forceinline__ void layer_tiles(
 // staged in LDS once per block.  With DEC the layer is the last one and the
 // decoder follows on the tile: z = tau_2 (ReLU(Y W3 + c3) W4 + c4), Eq. (6).
 // ---------------------------------------------------------------------------
-template <int D, int H, bool DEC, typename ZT>
+template <int D, int H, bool DEC, bool B1, typename ZT>
 __device__ __forceinline__ void layer_tiles_bf16(
     int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const uint16_t *__restrict__ ahat, const uint16_t *__restrict__ X, uint16_t *__restrict__ Y,
@@ -733,8 +733,9 @@ __device__ __forceinline__ void layer_tiles_bf16(
         const uint32_t tt = (uint32_t)(t < ntiles ? t : ntiles - 1);
         const uint32_t r0 = tt * 16u;
         const uint32_t rlast = r0 + 15u < (uint32_t)rows ? r0 + 15u : (uint32_t)rows - 1u;
-        ifirst = r0 / (uint32_t)B;
-        nn = (int)(rlast / (uint32_t)B - ifirst) + 1;
+        // B1: one right-hand side, rows are nodes (no division)
+        ifirst = B1 ? r0 : r0 / (uint32_t)B;
+        nn = (int)((B1 ? rlast : rlast / (uint32_t)B) - ifirst) + 1;
     };
     auto fetch_rp = [&](int64_t t) -> int32_t {
         uint32_t ifirst;
@@ -815,7 +816,7 @@ __device__ __forceinline__ void layer_tiles_bf16(
             const int64_t r = r0 + rl;
             const bool valid = r < rows;
             const uint32_t rr = (uint32_t)(valid ? r : r0);
-            const uint32_t i = rr / (uint32_t)B;
+            const uint32_t i = B1 ? rr : rr / (uint32_t)B;
             const uint32_t b = rr - i * (uint32_t)B;
             const int li = (int)(i - ifirst);
             const int32_t ks = valid ? __shfl(rp0, li, WAVE) - kbeg : 0;
@@ -848,7 +849,11 @@ __device__ __forceinline__ void layer_tiles_bf16(
                     for (int u = 0; u < NB; ++u) {
                         const int32_t kk = k0 + u < CAP ? k0 + u : CAP - 1;
                         wgt[u] = sVa[wv][kk];
-                        raw[u] = buffer_chunk<CB>(xr, k0 + u < ke ? sCo[wv][kk] + lane_off : BUF_OOB);
+                        // past the row: the offset OR-ed up to BUF_OOB (the
+                        // staged value stays in use, so its read is not
+                        // moved into a branch)
+                        const uint32_t oob = k0 + u < ke ? 0u : BUF_OOB;
+                        raw[u] = buffer_chunk<CB>(xr, (sCo[wv][kk] + lane_off) | oob);
                     }
 #pragma unroll
                     for (int u = 0; u < NB; ++u) acc_chunk(raw[u], wgt[u]);
@@ -959,19 +964,25 @@ __global__ __launch_bounds__(BLOCK) void k_layer(GNP_LAYER_PARAMS) {
 
 // The bfloat16 layers (and the last one with the decoder), held to 128
 // registers: at least 4 wavefronts per SIMD.
-template <typename G, int D, int H, bool DEC, typename ZT>
+template <typename G, int D, int H, bool DEC, typename ZT, bool B1 = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_layer_w4(
     GNP_LAYER_PARAMS) {
     static_assert(sizeof(G) == 2, "bfloat16 layer");
-    layer_tiles_bf16<D, H, DEC, ZT>(rows, B, rp, ci, ahat, X, Y, wcat, w3, vec, oc3, oW4, oc4, tau,
-                                    z, skip);
+    layer_tiles_bf16<D, H, DEC, B1, ZT>(rows, B, rp, ci, ahat, X, Y, wcat, w3, vec, oc3, oW4, oc4,
+                                        tau, z, skip);
 }
 #undef GNP_LAYER_PARAMS
 #undef GNP_LAYER_ARGS
 
-// The layer kernel to launch for a configuration.
-template <typename G, int D, int H, bool DEC, typename ZT> inline auto layer_kernel() {
-    if constexpr (sizeof(G) == 2) return &k_layer_w4<G, D, H, DEC, ZT>;
+// The layer kernel to launch for a configuration (B: right-hand sides
+// interleaved in the activations; the bfloat16 kernel has a variant for one).
+template <typename G, int D, int H, bool DEC, typename ZT>
+inline void (*layer_kernel(int B = 0))(int64_t, int, const int32_t *, const int32_t *,
+                                        const typename Act<G>::vt *, const G *, G *, const void *,
+                                        const void *, const typename Act<G>::acc *, int64_t,
+                                        int64_t, int64_t, const double *, ZT *, const int *) {
+    if constexpr (sizeof(G) == 2)
+        return B == 1 ? &k_layer_w4<G, D, H, DEC, ZT, true> : &k_layer_w4<G, D, H, DEC, ZT, false>;
     else return &k_layer<G, D, H, DEC, ZT>;
 }
 
