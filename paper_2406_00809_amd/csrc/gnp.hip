@@ -209,13 +209,13 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
     for (int l = 0; l < m->L; ++l) {
         const G *X = buf(l);
         if (l < m->L - 1 || layers) {
-            hipLaunchKernelGGL((layer_kernel<G, D, H, false, ZT>(nrhs)),
+            hipLaunchKernelGGL((layer_kernel<G, D, H, false, ZT>(nrhs, s->max_row)),
                                dim3(layer_grid<G, D, H, false, ZT>(rows)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, buf(l + 1), wcat(l), w3, vec,
                                po.c3, po.W4, po.c4, tau, z, skip);
         }
         if (l == m->L - 1) {
-            hipLaunchKernelGGL((layer_kernel<G, D, H, true, ZT>(nrhs)),
+            hipLaunchKernelGGL((layer_kernel<G, D, H, true, ZT>(nrhs, s->max_row)),
                                dim3(layer_grid<G, D, H, true, ZT>(rows)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, (G *)nullptr, wcat(l), w3, vec, po.c3,
                                po.W4, po.c4, tau, z, skip);
@@ -288,7 +288,7 @@ static void layer_once(gnp_model *m, int nrhs, int l, hipStream_t st) {
         ahat = (const typename Act<G>::vt *)s->ahat16;
         vec = (const typename Act<G>::acc *)m->theta32;
     }
-    hipLaunchKernelGGL((layer_kernel<G, D, H, false, float>(nrhs)), dim3(grid), dim3(BLOCK), 0, st, rows,
+    hipLaunchKernelGGL((layer_kernel<G, D, H, false, float>(nrhs, s->max_row)), dim3(grid), dim3(BLOCK), 0, st, rows,
                        nrhs, s->rp, s->ci, ahat, (const G *)m->ws.act[0], (G *)m->ws.act[1], wc,
                        (const void *)nullptr, vec, m->po.c3, m->po.W4, m->po.c4,
                        (const double *)m->ws.tau, (float *)nullptr, (const int *)nullptr);

@@ -681,7 +681,7 @@ __device__ __forceinline__ void layer_tiles(
 // staged in LDS once per block.  With DEC the layer is the last one and the
 // decoder follows on the tile: z = tau_2 (ReLU(Y W3 + c3) W4 + c4), Eq. (6).
 // ---------------------------------------------------------------------------
-template <int D, int H, bool DEC, bool B1, typename ZT>
+template <int D, int H, bool DEC, bool B1, bool SHORT, typename ZT>
 __device__ __forceinline__ void layer_tiles_bf16(
     int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const uint16_t *__restrict__ ahat, const uint16_t *__restrict__ X, uint16_t *__restrict__ Y,
@@ -691,10 +691,12 @@ __device__ __forceinline__ void layer_tiles_bf16(
     if (skip && *skip) return;
     using G = uint16_t;
     constexpr int LD = 2 * D + lds_pad<G>();
-    constexpr int CAP = 256, NC = CAP / WAVE;
+    // SHORT (every row has at most 7 entries): 7 neighbour slots per batch
+    // and a 128-entry CSR slice (16 rows x 7 fit); otherwise 8 and 256
+    constexpr int CAP = SHORT ? 128 : 256, NC = CAP / WAVE;
     constexpr int KB = 2 * D / 32, NT = D / 16;  // MFMA k-blocks and n-tiles
     constexpr int CB = (D / 4) * (int)sizeof(G);  // bytes per lane per row
-    constexpr int NB = 8;                         // neighbour loads per batch
+    constexpr int NB = SHORT ? 7 : 8;             // neighbour loads per batch
     constexpr int KP = ((D + 31) / 32) * 32;      // decoder K, zero-padded
     constexpr int NW3 = DEC ? (KP / 32) * (H / 16) * WAVE : 1;  // W3 fragments (x 8 bf16)
     __shared__ __attribute__((aligned(16))) G As[BLOCK / WAVE][16][LD];
@@ -964,26 +966,35 @@ __global__ __launch_bounds__(BLOCK) void k_layer(GNP_LAYER_PARAMS) {
 
 // The bfloat16 layers (and the last one with the decoder), held to 128
 // registers: at least 4 wavefronts per SIMD.
-template <typename G, int D, int H, bool DEC, typename ZT, bool B1 = false>
+template <typename G, int D, int H, bool DEC, typename ZT, bool B1 = false, bool SHORT = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_layer_w4(
     GNP_LAYER_PARAMS) {
     static_assert(sizeof(G) == 2, "bfloat16 layer");
-    layer_tiles_bf16<D, H, DEC, B1, ZT>(rows, B, rp, ci, ahat, X, Y, wcat, w3, vec, oc3, oW4, oc4,
-                                        tau, z, skip);
+    layer_tiles_bf16<D, H, DEC, B1, SHORT, ZT>(rows, B, rp, ci, ahat, X, Y, wcat, w3, vec, oc3, oW4,
+                                               oc4, tau, z, skip);
 }
 #undef GNP_LAYER_PARAMS
 #undef GNP_LAYER_ARGS
 
 // The layer kernel to launch for a configuration (B: right-hand sides
-// interleaved in the activations; the bfloat16 kernel has a variant for one).
+// interleaved in the activations; max_row: the longest row of the matrix).
+// The bfloat16 kernel has variants for one right-hand side and for rows of
+// at most 7 entries (7-point stencils and sparser).
 template <typename G, int D, int H, bool DEC, typename ZT>
-inline void (*layer_kernel(int B = 0))(int64_t, int, const int32_t *, const int32_t *,
-                                        const typename Act<G>::vt *, const G *, G *, const void *,
-                                        const void *, const typename Act<G>::acc *, int64_t,
-                                        int64_t, int64_t, const double *, ZT *, const int *) {
-    if constexpr (sizeof(G) == 2)
-        return B == 1 ? &k_layer_w4<G, D, H, DEC, ZT, true> : &k_layer_w4<G, D, H, DEC, ZT, false>;
-    else return &k_layer<G, D, H, DEC, ZT>;
+inline void (*layer_kernel(int B = 0, int max_row = 0))(
+    int64_t, int, const int32_t *, const int32_t *, const typename Act<G>::vt *, const G *, G *,
+    const void *, const void *, const typename Act<G>::acc *, int64_t, int64_t, int64_t,
+    const double *, ZT *, const int *) {
+    if constexpr (sizeof(G) == 2) {
+        const bool shrt = max_row > 0 && max_row <= 7;
+        if (B == 1)
+            return shrt ? &k_layer_w4<G, D, H, DEC, ZT, true, true>
+                        : &k_layer_w4<G, D, H, DEC, ZT, true, false>;
+        return shrt ? &k_layer_w4<G, D, H, DEC, ZT, false, true>
+                    : &k_layer_w4<G, D, H, DEC, ZT, false, false>;
+    } else {
+        return &k_layer<G, D, H, DEC, ZT>;
+    }
 }
 
 // Grid of the persistent layer kernel: as many blocks as can be resident at
