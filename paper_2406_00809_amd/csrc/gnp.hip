@@ -210,13 +210,13 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
         const G *X = buf(l);
         if (l < m->L - 1 || layers) {
             hipLaunchKernelGGL((layer_kernel<G, D, H, false, ZT>(nrhs, s->max_row)),
-                               dim3(layer_grid<G, D, H, false, ZT>(rows)), dim3(BLOCK), 0, st, rows,
+                               dim3(layer_grid<G, D, H, false, ZT>(rows, nrhs, s->max_row)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, buf(l + 1), wcat(l), w3, vec,
                                po.c3, po.W4, po.c4, tau, z, skip);
         }
         if (l == m->L - 1) {
             hipLaunchKernelGGL((layer_kernel<G, D, H, true, ZT>(nrhs, s->max_row)),
-                               dim3(layer_grid<G, D, H, true, ZT>(rows)), dim3(BLOCK), 0, st, rows,
+                               dim3(layer_grid<G, D, H, true, ZT>(rows, nrhs, s->max_row)), dim3(BLOCK), 0, st, rows,
                                nrhs, s->rp, s->ci, ahat, X, (G *)nullptr, wcat(l), w3, vec, po.c3,
                                po.W4, po.c4, tau, z, skip);
         }
@@ -271,7 +271,7 @@ template <typename G, int D, int H>
 static void layer_once(gnp_model *m, int nrhs, int l, hipStream_t st) {
     gnp_system *s = m->sys;
     const int64_t rows = s->n * (int64_t)nrhs;
-    const int grid = layer_grid<G, D, H, false, float>(rows);
+    const int grid = layer_grid<G, D, H, false, float>(rows, nrhs, s->max_row);
     const void *wc;
     const typename Act<G>::vt *ahat;
     const typename Act<G>::acc *vec;

@@ -998,17 +998,22 @@ inline void (*layer_kernel(int B = 0, int max_row = 0))(
 }
 
 // Grid of the persistent layer kernel: as many blocks as can be resident at
-// once (occupancy x compute units), at most one 64-row block per tile group.
+// once (the occupancy of the variant launched x compute units), at most one
+// 64-row block per tile group.  B, max_row: as for layer_kernel.
 template <typename G, int D, int H, bool DEC, typename ZT>
-inline int layer_grid(int64_t rows) {
-    static const int resident = [] {  // initialised once, thread-safe
-        int dev = 0, cus = 0, per_cu = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, layer_kernel<G, D, H, DEC, ZT>(), BLOCK, 0);
-        return (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
-    }();
+inline int layer_grid(int64_t rows, int B = 0, int max_row = 0) {
+    int resident;
+    if constexpr (sizeof(G) == 2) {
+        const bool shrt = max_row > 0 && max_row <= 7;
+        if (B == 1)
+            resident = shrt ? resident_blocks<&k_layer_w4<G, D, H, DEC, ZT, true, true>>()
+                            : resident_blocks<&k_layer_w4<G, D, H, DEC, ZT, true, false>>();
+        else
+            resident = shrt ? resident_blocks<&k_layer_w4<G, D, H, DEC, ZT, false, true>>()
+                            : resident_blocks<&k_layer_w4<G, D, H, DEC, ZT, false, false>>();
+    } else {
+        resident = resident_blocks<&k_layer<G, D, H, DEC, ZT>>();
+    }
     const int64_t need = (rows + 63) / 64;
     int g = (int)(need < resident ? need : resident);
     return g >= XCDS ? g - g % XCDS : g;  // whole rounds over the XCDs
