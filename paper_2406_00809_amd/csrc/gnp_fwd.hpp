@@ -239,17 +239,6 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     __shared__ double sh[BLOCK / WAVE];
     const int lane = threadIdx.x % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    double tau1 = 0.0;  // sqrt(n) / tau when the triple is formed here
-    if (tau_partial) {
-        const double tv = sqrt(sum_partials(tau_nblk, tau_partial, 1, sh));
-        const double sqn = sqrt((double)n);
-        tau1 = tv > 0.0 ? sqn / tv : 0.0;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            tau[0] = tv;
-            tau[1] = tau1;
-            tau[2] = tv / sqn;
-        }
-    }
     const float *W1 = vec + oW1, *c1 = vec + oc1, *c2 = vec + oc2;
     // hidden-unit weights in the layout of the MFMA B operand, output bias in
     // the result layout, W2 fragments as the A operand
@@ -283,12 +272,33 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     const int64_t ntiles = (rows + 15) / 16, nw = (int64_t)gridDim.x * (BLOCK / WAVE);
     int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
     IN vn = v[t * 16 + lane % 16 < rows ? t * 16 + lane % 16 : rows - 1];
+    // without tau_partial: sqrt(n)/tau of every right-hand side (B <= 256)
+    // staged in LDS once, so the tile loop waits on no global load but its
+    // input prefetch
+    __shared__ double s_tau1[BLOCK];
+    if (!tau_partial)
+        for (int b = threadIdx.x; b < B; b += BLOCK) s_tau1[b] = tau[3 * b + 1];
+    // the weights and the first input are in flight while tau is summed
+    double tau1 = 0.0;  // sqrt(n) / tau when the triple is formed here
+    if (!tau_partial) __syncthreads();  // s_tau1 complete
+    if (tau_partial) {
+        const double tv = sqrt(sum_partials(tau_nblk, tau_partial, 1, sh));
+        const double sqn = sqrt((double)n);
+        tau1 = tv > 0.0 ? sqn / tv : 0.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            tau[0] = tv;
+            tau[1] = tau1;
+            tau[2] = tv / sqn;
+        }
+    }
     for (; t < ntiles; t += nw) {
         const int64_t ra = t * 16 + lane % 16;
         const IN vc = vn;
+        // this tile's scale first, then the next tile's input: waiting for
+        // the scale leaves the prefetch in flight
+        const double ts = tau_partial ? tau1 : s_tau1[(uint32_t)ra % (uint32_t)B];
         const int64_t rn = (t + nw) * 16 + lane % 16;
         vn = v[rn < rows ? rn : rows - 1];  // next tile's input, clamped
-        const double ts = tau_partial ? tau1 : tau[3 * ((uint32_t)ra % (uint32_t)B) + 1];
         const float u = ra < rows ? (float)(ts * (double)vc) : 0.f;
         f32x4 o[D / 16];
 #pragma unroll
