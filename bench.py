@@ -262,6 +262,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
+    ap.add_argument("--sampler-compare", action="store_true",
+                    help="also train a network with the Arnoldi sampler of Eq. (3) (m = 40, "
+                         "half of every batch) and report its iterations and solves/s")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the float32-network comparison solves")
     args = ap.parse_args()
@@ -429,6 +432,31 @@ def main():
         extra["spmv_f32_bandwidth_powerlaw_2^20"] = {"nnz": A3.nnz, **spmv_bandwidth(S3, dev)}
         S3.close()
         log("spmv", extra["spmv_f32_bandwidth"], extra["spmv_f32_bandwidth_powerlaw_2^20"])
+
+    if args.sampler_compare:
+        # the paper's training data (Sec. 3): 16 of 32 columns of every batch
+        # from Eq. (3) with m = 40 Arnoldi steps, the rest x ~ N(0, I); same
+        # initial weights, steps and seed as the default network
+        M2 = api.Model(S, L, d, h, th0)
+        t1 = time.perf_counter()
+        h2, b2 = M2.train(args.train_steps, 32, lr=1e-3, seed=2, prec="f32", sampler_m=40,
+                          sampler_count=16)
+        torch.cuda.synchronize()
+        tr2 = time.perf_counter() - t1
+        x2 = torch.zeros(S.n, dtype=torch.float64, device=dev)
+        api.fgmres_solve(S, b, M2, x=x2, m=m, rtol=1e-8, maxiters=args.maxiters, prec=args.prec,
+                         want_hist=False)
+        x2.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, inf2, _ = api.fgmres_solve(S, b, M2, x=x2, m=m, rtol=1e-8, maxiters=args.maxiters,
+                                      prec=args.prec, want_hist=False)
+        torch.cuda.synchronize()
+        extra["sampler_trained"] = {"solves_per_s": 1.0 / (time.perf_counter() - t1),
+                                    "iters": inf2["iters"], "converged": inf2["converged"],
+                                    "rel_res_true": inf2["rel_res_true"], "train_s": tr2,
+                                    "train_loss_first_best": [float(h2[0]), float(h2[b2])]}
+        log(f"sampler-trained network: {inf2['iters']} its, {extra['sampler_trained']}")
 
     # ---- dominant kernel: one Res-GCONV layer, same launch configuration
     lay_ms = M.time_layer(nrhs=1, prec=args.prec, reps=200)
