@@ -133,10 +133,17 @@ def test_gnp_apply_single_rhs(api, case, prec):
     assert err < TOL[prec], err
 
 
+MULTI = {
+    "convdiff3d_10": lambda: I.convdiff3d(10),  # rows of at most 7 entries
+    "powerlaw_5000": lambda: I.powerlaw_random(5000, seed_structure=15, seed_values=16),
+}
+
+
+@pytest.mark.parametrize("mat", list(MULTI))
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("nrhs", [3, 32])
-def test_gnp_apply_multi_rhs_and_zero_column(api, prec, nrhs):
-    A = I.convdiff3d(10)
+def test_gnp_apply_multi_rhs_and_zero_column(api, prec, nrhs, mat):
+    A = MULTI[mat]()
     S = api.System(A)
     ref = O.System(A)
     L, d, h = 4, 32, 64
