@@ -72,10 +72,6 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
     return s;
 }
 
-// Grid-level "last block" detection for deterministic two-stage reductions:
-// every block writes its partials, then calls this; exactly one block (the
-// last to arrive) gets true and may read all partials, which it sums in
-// block order.  The ticket counter is reset by that block.
 // Sum of partial[k * stride] over k < nblk in one fixed order (every thread
 // of the block takes part and receives the sum): any block that calls it on
 // the same data gets the same bits.  scratch: >= BLOCK / WAVE doubles.
@@ -96,6 +92,10 @@ __device__ __forceinline__ double sum_partials(int nblk, const double *__restric
     return block_sum((a[0] + a[1]) + (a[2] + a[3]), scratch);
 }
 
+// Grid-level "last block" detection for deterministic two-stage reductions:
+// every block writes its partials, then calls this; exactly one block (the
+// last to arrive) gets true and may read all partials, which it sums in
+// block order.  The ticket counter is reset by that block.
 __device__ __forceinline__ bool last_block(unsigned *counter) {
     __shared__ int is_last;
     __threadfence();
@@ -113,7 +113,7 @@ __device__ __forceinline__ bool last_block(unsigned *counter) {
 }
 
 // ---------------------------------------------------------------------------
-// precision selection
+// tile walk of the persistent kernels
 // ---------------------------------------------------------------------------
 // Tile walk of a persistent grid that keeps every XCD on one contiguous range
 // of tiles.  MI355X dispatches workgroups to its 8 XCDs round-robin (block b
@@ -145,6 +145,7 @@ __device__ __forceinline__ TileWalk xcd_walk(int64_t ntiles, int waves_per_block
     return w;
 }
 
+// precision selection
 inline bool valid_precision(int p) { return p == GNP_F64 || p == GNP_F32 || p == GNP_BF16; }
 
 inline int grid_for(int64_t work, int per_block, int cap = 1 << 20) {
