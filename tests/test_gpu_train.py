@@ -187,6 +187,36 @@ def test_train_f32_full_shape_loss_decreases(api):
     assert hist[best] < 0.9 * hist[0]
 
 
+def test_teacher_forcing_full_shape(api):
+    """Gradients at weights the GPU has trained: the full training shape
+    (64^3 convection-diffusion, L = 8, d = 32, h = 64) is trained on the GPU
+    in FP32 with fresh batches of 32; at steps 0, 100 and 400 the weights are
+    handed to the oracle, and the loss and gradient on a fixed two-column
+    batch are compared in FP64 and FP32.  The oracle cannot afford the
+    training run itself; this checks the backward pass where training
+    actually goes, with ReLU patterns unlike those of the initial weights.
+    (Adam restarts at each stage: any weights the GPU produced will do.)"""
+    A = I.convdiff3d(64)
+    S = api.System(A)
+    ref = O.System(A)
+    L, d, h = 8, 32, 64
+    M = api.Model(S, L, d, h, I.init_params(L, d, h, 12))
+    b_np = O.spmm(ref.A, np.random.default_rng(28).standard_normal((A.n, 2)))
+    b = _dev(b_np)
+    done = 0
+    for k in (0, 100, 400):
+        if k > done:
+            M.train(k - done, 32, lr=1e-3, seed=2 + k, prec="f32")
+            done = k
+        th = M.get_params()
+        lr, gr = O.loss_grad(ref, L, d, h, th, b_np)
+        for prec, tl, tg in (("f64", 1e-12, 1e-10), ("f32", 1e-5, 2e-3)):
+            loss, g = M.loss_grad(b, prec=prec)
+            el, eg = abs(loss - lr) / lr, _nrel(g, gr)
+            print(f"step {k} {prec}: loss {loss:.6f} (oracle {lr:.6f}) err {el:.2e}, grad err {eg:.2e}")
+            assert el < tl and eg < tg, (k, prec, el, eg)
+
+
 def test_autograd_function_matches_oracle(api):
     import torch
     from paper_2406_00809_amd.autograd import gnp
