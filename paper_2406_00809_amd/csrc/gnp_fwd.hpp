@@ -223,20 +223,20 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
 // ---------------------------------------------------------------------------
 // Persistent encoder for the MFMA paths (float32 / bfloat16 activations):
 // the weights a lane needs are loaded once, and the input of the next tile
-// is requested before the current one is computed.  With tau_partial (a
-// single right-hand side), every block first forms the tau triple of Eq. (6)
-// itself from the per-block sums of squares of v (the same fixed-order sum
-// in every block) and block 0 publishes it for the decoder.
+// is requested before the current one is computed.  With hdiv (one
+// right-hand side, inside the solver) the input is the orthogonalised
+// vector w and the network input is the next basis vector v = w / *hdiv,
+// rounded as the basis stores it and written to vout; its tau of Eq. (6) is
+// 1 (v has unit norm), and block 0 publishes that triple for the decoder.
 // ---------------------------------------------------------------------------
 template <typename G, typename IN, int D, int H>
 __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     int64_t rows, int B, const IN *__restrict__ v, double *__restrict__ tau,
     const float *__restrict__ vec, int64_t oW1, int64_t oc1, int64_t oc2,
     const void *__restrict__ w2, G *__restrict__ E, const int *__restrict__ skip,
-    const double *__restrict__ tau_partial, int tau_nblk, int64_t n) {
+    const double *__restrict__ hdiv, IN *__restrict__ vout, int64_t n) {
     static_assert(sizeof(G) <= 4, "MFMA encoder");
     if (skip && *skip) return;
-    __shared__ double sh[BLOCK / WAVE];
     const int lane = threadIdx.x % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const float *W1 = vec + oW1, *c1 = vec + oc1, *c2 = vec + oc2;
@@ -272,19 +272,18 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     const int64_t ntiles = (rows + 15) / 16, nw = (int64_t)gridDim.x * (BLOCK / WAVE);
     int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
     IN vn = v[t * 16 + lane % 16 < rows ? t * 16 + lane % 16 : rows - 1];
-    // without tau_partial: sqrt(n)/tau of every right-hand side (B <= 256)
-    // staged in LDS once, so the tile loop waits on no global load but its
-    // input prefetch
+    // without hdiv: sqrt(n)/tau of every right-hand side (B <= 256) staged in
+    // LDS once, so the tile loop waits on no global load but its input
+    // prefetch
     __shared__ double s_tau1[BLOCK];
-    if (!tau_partial)
+    double tau1 = 0.0, div = 1.0;  // with hdiv: sqrt(n) / 1 and the divisor
+    if (!hdiv) {
         for (int b = threadIdx.x; b < B; b += BLOCK) s_tau1[b] = tau[3 * b + 1];
-    // the weights and the first input are in flight while tau is summed
-    double tau1 = 0.0;  // sqrt(n) / tau when the triple is formed here
-    if (!tau_partial) __syncthreads();  // s_tau1 complete
-    if (tau_partial) {
-        const double tv = sqrt(sum_partials(tau_nblk, tau_partial, 1, sh));
-        const double sqn = sqrt((double)n);
-        tau1 = tv > 0.0 ? sqn / tv : 0.0;
+        __syncthreads();
+    } else {
+        const double sqn = sqrt((double)n), tv = 1.0;
+        tau1 = sqn / tv;
+        div = *hdiv;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             tau[0] = tv;
             tau[1] = tau1;
@@ -293,10 +292,12 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     }
     for (; t < ntiles; t += nw) {
         const int64_t ra = t * 16 + lane % 16;
-        const IN vc = vn;
+        // with hdiv: the basis vector, as the solver's normalisation forms it
+        const IN vc = hdiv ? (IN)((double)vn / div) : vn;
+        if (hdiv && vout && lane < 16 && ra < rows) vout[ra] = vc;
         // this tile's scale first, then the next tile's input: waiting for
         // the scale leaves the prefetch in flight
-        const double ts = tau_partial ? tau1 : s_tau1[(uint32_t)ra % (uint32_t)B];
+        const double ts = hdiv ? tau1 : s_tau1[(uint32_t)ra % (uint32_t)B];
         const int64_t rn = (t + nw) * 16 + lane % 16;
         vn = v[rn < rows ? rn : rows - 1];  // next tile's input, clamped
         const float u = ra < rows ? (float)(ts * (double)vc) : 0.f;

@@ -98,12 +98,14 @@ void launch_colnorm(gnp_model *m, const IN *v, int nrhs, double *tau_out, double
 // z = M(v) given precomputed tau triples.  act0/act1: activation buffers.
 // When layers != nullptr, X_0 (encoder output) and every layer output X_l
 // are kept in block l of layers ((L+1) blocks of n * nrhs * d activations)
-// instead of ping-ponging between act0 and act1.  With tau_partial (one
-// float32/bfloat16 right-hand side) the encoder forms the tau triple from the
-// per-block sums of squares of v and writes it to tau.
+// instead of ping-ponging between act0 and act1.  With hdiv (one
+// float32/bfloat16 right-hand side, inside the solver) v is the
+// orthogonalised vector w: the encoder forms the next basis vector w / *hdiv
+// (stored to vout when given) and feeds it to the network with tau = 1,
+// writing that triple to tau.
 gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                           const double *tau, void *act0, void *act1, const int *skip,
-                          hipStream_t st, void *layers = nullptr,
-                          const double *tau_partial = nullptr, int tau_nblk = 0);
+                          hipStream_t st, void *layers = nullptr, const double *hdiv = nullptr,
+                          void *vout = nullptr);
 
 }  // namespace gnp

@@ -183,58 +183,48 @@ __global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *
 }
 
 // ---------------------------------------------------------------------------
-// v = src / div into vcur (contiguous); partial ||v||^2 of the stored
-// (rounded) values.  div = beta (cycle start) or h_{j+1,j}.  The basis
-// column of v is written by the next step's first Gram-Schmidt pass, which
-// reads that row of the basis anyway.
+// v = src / div into vcur (contiguous), div = beta (cycle start) or
+// h_{j+1,j}.  The basis column of v is written by the next step's first
+// Gram-Schmidt pass, which reads that row of the basis anyway.  (With a
+// float32/bfloat16 network the encoder does this division itself for
+// j >= 1, with the same expression.)
 // ---------------------------------------------------------------------------
 template <typename KT, typename ST>
 __global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__restrict__ src,
-                                                     KT *__restrict__ vcur,
-                                                     double *__restrict__ partial, const Ctl *ctl,
+                                                     KT *__restrict__ vcur, const Ctl *ctl,
                                                      int use_beta, Bat bt) {
     const int bi = blockIdx.y;
     ctl += bi;
     if (ctl->cycle_done) return;
-    __shared__ double sh[BLOCK / WAVE];
     src += bi * bt.vec;
-    partial += bi * bt.part;
     const double div = use_beta ? ctl->beta : ctl->hnext;
-    double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * BLOCK) {
-        const KT t = (KT)((double)src[i] / div);
-        vcur[i * bt.vstep + bi] = t;
-        s += (double)t * (double)t;
-    }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+         i += (int64_t)gridDim.x * BLOCK)
+        vcur[i * bt.vstep + bi] = (KT)((double)src[i] / div);
 }
 
-// tau triple (tau, sqrt(n)/tau, tau/sqrt(n)) of the network input, Eq. (6)
-// In a batch (gridDim.y right-hand sides), block (0, 0) also records in
-// *all_done whether every right-hand side has ended its cycle (the network
-// launches of the next step are then skipped).
-__global__ __launch_bounds__(BLOCK) void k_fin_tau(int nblk, const double *partial, int64_t n,
-                                                   double *tau, const Ctl *ctl, Bat bt,
-                                                   int *all_done) {
-    if (all_done && blockIdx.y == 0 && threadIdx.x == 0) {
+// tau triple (tau, sqrt(n)/tau, tau/sqrt(n)) of the network input, Eq. (6).
+// Every network input of the solver is a basis vector v = w / ||w||, whose
+// norm is 1 in exact arithmetic; tau is taken as that 1 (the norm of the
+// rounded vector differs from it by about one unit of its precision), which
+// spares a global reduction per Arnoldi step.  In a batch (gridDim.y
+// right-hand sides) block (0, 0) also records in *all_done whether every
+// right-hand side has ended its cycle (the network launches of the next step
+// are then skipped).
+__global__ void k_unit_tau(int64_t n, double *tau, const Ctl *ctl, int *all_done) {
+    if (threadIdx.x != 0) return;
+    if (all_done && blockIdx.y == 0) {
         int done = 1;
         for (int k = 0; k < (int)gridDim.y; ++k) done &= ctl[k].cycle_done ? 1 : 0;
         *all_done = done;
     }
     ctl += blockIdx.y;
     if (ctl->cycle_done) return;
-    __shared__ double res[1];
-    partial += blockIdx.y * bt.part;
     tau += 3 * blockIdx.y;
-    reduce_columns(nblk, 1, partial, 1, res);
-    if (threadIdx.x == 0) {
-        const double tv = sqrt(res[0]), sqn = sqrt((double)n);
-        tau[0] = tv;
-        tau[1] = tv > 0.0 ? sqn / tv : 0.0;
-        tau[2] = tv / sqn;
-    }
+    const double tv = 1.0, sqn = sqrt((double)n);
+    tau[0] = tv;
+    tau[1] = sqn / tv;
+    tau[2] = tv / sqn;
 }
 
 // ---------------------------------------------------------------------------
@@ -666,21 +656,22 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     const int gcgs = (int)((n + rpb - 1) / rpb);
     const int pstride = MP + 1;
     const int *skip = &c->ctl->cycle_done;
-    // tau of the network input: formed by the encoder from the normalisation
-    // partials (float32/bfloat16 networks) or by its own kernel (float64);
-    // not needed without a network
-    const bool tau_in_encoder = model && c->prec != GNP_F64;
-    const bool tau_kernel = model && !tau_in_encoder;
+    // the basis vector v_j (j >= 1) = w / h_{j,j-1}: formed by the encoder of
+    // a float32/bfloat16 network as it reads w (it also stores v_j to vcur),
+    // else by its own kernel at the end of step j - 1
+    const bool v_in_encoder = model && c->prec != GNP_F64;
     hipLaunchKernelGGL((k_normalize<KT, double>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, vcur,
-                       c->partial, c->ctl, 1, Bat{});
-    if (tau_kernel)
-        hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
-                           c->ctl, Bat{}, (int *)nullptr);
+                       c->ctl, 1, Bat{});
+    if (model)
+        hipLaunchKernelGGL(k_unit_tau, dim3(1), dim3(WAVE), 0, st, n, c->tau, c->ctl,
+                           (int *)nullptr);
     for (int j = 0; j < nsteps; ++j) {
         KT *zj = model ? Z + (int64_t)j * n : vcur;
+        const bool fuse = v_in_encoder && j > 0;
         if (model)
-            GNP_TRY(forward_launch(model, c->prec, vcur, zj, 1, c->tau, c->act[0], c->act[1], skip,
-                                   st, nullptr, tau_in_encoder ? c->partial : nullptr, sg));
+            GNP_TRY(forward_launch(model, c->prec, fuse ? w : vcur, zj, 1, c->tau, c->act[0],
+                                   c->act[1], skip, st, nullptr,
+                                   fuse ? &c->ctl->hnext : nullptr, fuse ? vcur : nullptr));
         spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st, 1, 1, 0, 0,
                                 s->max_row);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
@@ -700,11 +691,13 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                            (const double *)c->partial, pstride, (const double *)c->h1,
                            (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
                            c->hist, Bat{});
-        hipLaunchKernelGGL((k_normalize<KT, KT>), dim3(sg), dim3(BLOCK), 0, st, n,
-                           (const KT *)w, vcur, c->partial, c->ctl, 0, Bat{});
-        if (tau_kernel)
-            hipLaunchKernelGGL(k_fin_tau, dim3(1), dim3(BLOCK), 0, st, sg, c->partial, n, c->tau,
-                               c->ctl, Bat{}, (int *)nullptr);
+        if (!v_in_encoder) {
+            hipLaunchKernelGGL((k_normalize<KT, KT>), dim3(sg), dim3(BLOCK), 0, st, n,
+                               (const KT *)w, vcur, c->ctl, 0, Bat{});
+            if (model)
+                hipLaunchKernelGGL(k_unit_tau, dim3(1), dim3(WAVE), 0, st, n, c->tau, c->ctl,
+                                   (int *)nullptr);
+        }
     }
     hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(BLOCK), 0, st, c->ctl, c->H, c->g, c->y, Bat{});
     if (model)
@@ -914,9 +907,9 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
     const int pstride = MP + 1;
     float *V = c->V, *w = c->w;
     hipLaunchKernelGGL((k_normalize<float, double>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
-                       (const double *)c->r, c->vpk, c->partial, (const Ctl *)c->ctl, 1, bt);
-    hipLaunchKernelGGL(k_fin_tau, dim3(1, nb), dim3(BLOCK), 0, st, sg, (const double *)c->partial,
-                       n, c->tau, (const Ctl *)c->ctl, bt, c->all_done);
+                       (const double *)c->r, c->vpk, (const Ctl *)c->ctl, 1, bt);
+    hipLaunchKernelGGL(k_unit_tau, dim3(1, nb), dim3(WAVE), 0, st, n, c->tau,
+                       (const Ctl *)c->ctl, c->all_done);
     for (int j = 0; j < nsteps; ++j) {
         float *zj = c->Zp + (int64_t)j * n * nb;
         GNP_TRY(forward_launch(model, c->prec, c->vpk, zj, nb, c->tau, c->act[0], c->act[1],
@@ -942,10 +935,9 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
                            (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
                            c->hist, bt);
         hipLaunchKernelGGL((k_normalize<float, float>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
-                           (const float *)w, c->vpk, c->partial, (const Ctl *)c->ctl, 0, bt);
-        hipLaunchKernelGGL(k_fin_tau, dim3(1, nb), dim3(BLOCK), 0, st, sg,
-                           (const double *)c->partial, n, c->tau, (const Ctl *)c->ctl, bt,
-                           c->all_done);
+                           (const float *)w, c->vpk, (const Ctl *)c->ctl, 0, bt);
+        hipLaunchKernelGGL(k_unit_tau, dim3(1, nb), dim3(WAVE), 0, st, n, c->tau,
+                           (const Ctl *)c->ctl, c->all_done);
     }
     hipLaunchKernelGGL(k_backsolve, dim3(1, nb), dim3(BLOCK), 0, st, c->ctl, (const double *)c->H,
                        (const double *)c->g, c->y, bt);
