@@ -355,23 +355,30 @@ def main():
     # ---- comparison: float32 network (same weights), and unpreconditioned GMRES
     extra = {}
     if not args.no_compare:
+        def median_rate(run, reps=3):
+            """Median solves/s over `reps` timed solves (after one untimed)."""
+            run()
+            rates = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                info = run()
+                torch.cuda.synchronize()
+                rates.append(1.0 / (time.perf_counter() - t1))
+            return float(np.median(rates)), info
+
         for p in (["f32"] if args.prec != "f32" else []):
-            solve(p)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, inf2, _ = solve(p)
-            torch.cuda.synchronize()
-            extra[f"{p}_network"] = {"solves_per_s": 1.0 / (time.perf_counter() - t1),
-                                     "iters": inf2["iters"],
+            rate, inf2 = median_rate(lambda: solve(p)[1])
+            extra[f"{p}_network"] = {"solves_per_s": rate, "iters": inf2["iters"],
                                      "rel_res_true": inf2["rel_res_true"]}
-        x.zero_()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, inf3, _ = api.fgmres_solve(S, b, None, x=x, m=m, rtol=1e-8, maxiters=args.maxiters,
-                                      prec="f32", want_hist=False)
-        torch.cuda.synchronize()
-        extra["no_preconditioner"] = {"solves_per_s": 1.0 / (time.perf_counter() - t1),
-                                      "iters": inf3["iters"],
+
+        def plain():
+            x.zero_()
+            return api.fgmres_solve(S, b, None, x=x, m=m, rtol=1e-8, maxiters=args.maxiters,
+                                    prec="f32", want_hist=False)[1]
+
+        rate, inf3 = median_rate(plain)
+        extra["no_preconditioner"] = {"solves_per_s": rate, "iters": inf3["iters"],
                                       "rel_res_true": inf3["rel_res_true"]}
 
         # 32 right-hand sides b ~ N(0, I): float32 network one solve at a time,

@@ -231,7 +231,8 @@ __global__ void k_unit_tau(int64_t n, double *tau, const Ctl *ctl, int *all_done
 // Gram-Schmidt passes over the interleaved basis (8 lanes per row, lane q
 // owns entries k = 4 (q + 8 u) + e).  MODE 0: dots V_j^T w and ||w||^2;
 // column j (v_j) is taken from vcur and stored into the basis here.
-// MODE 1: w -= V_j hprev, then dots.  MODE 2: w -= V_j hprev, then ||w||^2.
+// MODE 1: w -= V_j hprev, then dots and ||w||^2 of the updated w.  MODE 2:
+// w -= V_j hprev only (its norm follows from MODE 1's sums, k_fin_givens).
 // Entries k > j are masked by selection (they may hold an older cycle).
 // ---------------------------------------------------------------------------
 template <typename KT> struct Quad;
@@ -334,9 +335,10 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
 #pragma unroll
                 for (int a = 0; a < NA; ++a) acc[a] += vv[a] * wi;
             }
-            if (MODE != 1 && q == 0) nrm += wi * wi;
+            if (MODE <= 1 && q == 0) nrm += wi * wi;
         }
     }
+    if constexpr (MODE == 2) return;  // no sums
     __shared__ double sh[BLOCK / WAVE][8 * NA + 1];
     const int lane = t % WAVE, wv = t / WAVE;
     if (MODE <= 1) {
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
             if (lane < 8) sh[wv][lane * NA + a] = s;
         }
     }
-    if (MODE != 1) {
+    {
         const double s = wave_sum(nrm);
         if (lane == 0) sh[wv][8 * NA] = s;
     }
@@ -363,15 +365,14 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
             dst[k] = s;
         }
     }
-    if (MODE != 1 && t == 0) {
+    if (t == 0) {
         double s = 0.0;
         for (int w2 = 0; w2 < BLOCK / WAVE; ++w2) s += sh[w2][8 * NA];
         dst[pstride - 1] = s;
     }
 }
 
-// dots finalize: hout[0..j] (and ||A z_j|| from the norm slot in MODE 0)
-template <int MODE>
+// first dots finalize: h1[0..j] and ||A z_j|| from the norm slot
 __global__ __launch_bounds__(BLOCK) void k_fin_dots(int nblk, int j, const double *partial,
                                                     int pstride, double *hout, Ctl *ctl, Bat bt) {
     ctl += blockIdx.y;
@@ -379,20 +380,24 @@ __global__ __launch_bounds__(BLOCK) void k_fin_dots(int nblk, int j, const doubl
     partial += blockIdx.y * bt.part;
     hout += blockIdx.y * bt.small;
     __shared__ double res[MAXCOL + 1];
-    // MODE 0 also sums the norm slot (last column of a partial row)
-    reduce_columns(nblk, j + 1, partial, pstride, res, MODE == 0 ? pstride - 1 : -1);
+    reduce_columns(nblk, j + 1, partial, pstride, res, pstride - 1);
     for (int k = threadIdx.x; k <= j; k += BLOCK) hout[k] = res[k];
-    if (MODE == 0 && threadIdx.x == 0) ctl->wnorm0 = sqrt(res[j + 1]);
+    if (threadIdx.x == 0) ctl->wnorm0 = sqrt(res[j + 1]);
 }
 
-// h_{j+1,j} = ||w||, column j of H-bar = h1 + h2, Givens rotation, residual
-// estimate, end-of-cycle decision.  Inputs are staged in LDS by all threads
-// (one round of loads), the sequential rotation runs in one thread on LDS.
+// End of an Arnoldi step, after the second pass: h2[0..j] = V^T w1 and
+// ||w1||^2 (w1: w after the first projection) from that pass's partials;
+// h_{j+1,j} = ||w1 - V h2|| = sqrt(||w1||^2 - ||h2||^2), exact for
+// orthonormal V and h2 = V^T w1 (h2 is a small correction, so nothing
+// cancels; a negative difference from rounding counts as 0, a breakdown);
+// column j of H-bar = h1 + h2, Givens rotation, residual estimate,
+// end-of-cycle decision.  The third pass then only updates w.  Inputs are
+// staged in LDS by all threads, the sequential rotation runs in one thread.
 __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const double *partial,
-                                                      int pstride, const double *h1,
-                                                      const double *h2, Ctl *ctl, double *H,
-                                                      double *H0, double *cs, double *sn,
-                                                      double *g, double *hist, Bat bt) {
+                                                      int pstride, const double *h1, double *h2,
+                                                      Ctl *ctl, double *H, double *H0,
+                                                      double *cs, double *sn, double *g,
+                                                      double *hist, Bat bt) {
     {
         const int bi = blockIdx.y;
         ctl += bi;
@@ -407,22 +412,27 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const dou
         if (hist) hist += bi * bt.hist;
     }
     if (ctl->cycle_done) return;
-    __shared__ double res[1];
+    __shared__ double res[MAXCOL + 1];
     __shared__ double col[MAXCOL], scs[MAXCOL], ssn[MAXCOL];
     __shared__ double gj_s;
     const int m = ctl->m;
-    for (int i = threadIdx.x; i <= j; i += BLOCK) {
-        col[i] = h1[i] + h2[i];
-        if (i < j) {
-            scs[i] = cs[i];
-            ssn[i] = sn[i];
-        }
+    for (int i = threadIdx.x; i < j; i += BLOCK) {
+        scs[i] = cs[i];
+        ssn[i] = sn[i];
     }
     if (threadIdx.x == 0) gj_s = g[j];
-    reduce_columns(nblk, 1, partial + (pstride - 1), pstride, res);  // ends with a barrier
-    const double hn = sqrt(res[0]);
-    for (int i = threadIdx.x; i <= j; i += BLOCK) H0[(int64_t)i * m + j] = col[i];
+    reduce_columns(nblk, j + 1, partial, pstride, res, pstride - 1);  // ends with a barrier
+    for (int i = threadIdx.x; i <= j; i += BLOCK) {
+        h2[i] = res[i];
+        col[i] = h1[i] + res[i];
+        H0[(int64_t)i * m + j] = col[i];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double hh = 0.0;
+        for (int i = 0; i <= j; ++i) hh += res[i] * res[i];
+        const double d2 = res[j + 1] - hh;
+        const double hn = d2 < 0.0 ? 0.0 : sqrt(d2);  // NaN stays NaN
         H0[(int64_t)(j + 1) * m + j] = hn;
         col[j + 1] = hn;
         // previous rotations (Saad 2003, Sec. 6.5.3), then a new one
@@ -677,20 +687,17 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
                            Bat{}, (const KT *)vcur);
-        hipLaunchKernelGGL(k_fin_dots<0>, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
+        hipLaunchKernelGGL(k_fin_dots, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, Bat{});
         hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)c->h1, c->partial, pstride, (const Ctl *)c->ctl,
                            Bat{}, (const KT *)nullptr);
-        hipLaunchKernelGGL(k_fin_dots<1>, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
-                           (const double *)c->partial, pstride, c->h2, c->ctl, Bat{});
+        hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
+                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, Bat{});
         hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)c->h2, c->partial, pstride, (const Ctl *)c->ctl,
                            Bat{}, (const KT *)nullptr);
-        hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
-                           (const double *)c->partial, pstride, (const double *)c->h1,
-                           (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
-                           c->hist, Bat{});
         if (!v_in_encoder) {
             hipLaunchKernelGGL((k_normalize<KT, KT>), dim3(sg), dim3(BLOCK), 0, st, n,
                                (const KT *)w, vcur, c->ctl, 0, Bat{});
@@ -920,20 +927,17 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
         hipLaunchKernelGGL((k_cgs<float, MP, 0>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
                            bt, (const float *)c->vpk);
-        hipLaunchKernelGGL(k_fin_dots<0>, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
+        hipLaunchKernelGGL(k_fin_dots, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, bt);
         hipLaunchKernelGGL((k_cgs<float, MP, 1>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)c->h1, c->partial, pstride, (const Ctl *)c->ctl,
                            bt, (const float *)nullptr);
-        hipLaunchKernelGGL(k_fin_dots<1>, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
-                           (const double *)c->partial, pstride, c->h2, c->ctl, bt);
+        hipLaunchKernelGGL(k_fin_givens, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
+                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, bt);
         hipLaunchKernelGGL((k_cgs<float, MP, 2>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)c->h2, c->partial, pstride, (const Ctl *)c->ctl,
                            bt, (const float *)nullptr);
-        hipLaunchKernelGGL(k_fin_givens, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
-                           (const double *)c->partial, pstride, (const double *)c->h1,
-                           (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
-                           c->hist, bt);
         hipLaunchKernelGGL((k_normalize<float, float>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
                            (const float *)w, c->vpk, (const Ctl *)c->ctl, 0, bt);
         hipLaunchKernelGGL(k_unit_tau, dim3(1, nb), dim3(WAVE), 0, st, n, c->tau,
