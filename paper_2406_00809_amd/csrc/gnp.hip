@@ -153,15 +153,14 @@ gnp_status model_workspace(gnp_model *m, int nrhs) {
 // layers (optional): (L+1) blocks of rows*D activations; when given, X_0 and
 // every layer output X_l go to block l (the last layer then runs once more
 // without the decoder to materialise X_L).
-// hdiv (optional, one right-hand side, MFMA paths): v is the solver's
-// orthogonalised vector w; the encoder divides it by *hdiv into the next
-// basis vector (also stored to vout when given), takes tau = 1 for it and
-// stores that triple in tau.
+// bn (optional, one right-hand side, MFMA paths): v is the solver's vector
+// w; the encoder forms the next basis vector from it (BasisNext), takes
+// tau = 1 for it and stores that triple in tau.
 template <typename G, typename IN, typename ZT, int D, int H>
 static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const double *tau,
                           G *act0, G *act1, const typename Act<G>::acc *vec, const void *wmat,
                           const int *skip, hipStream_t st, G *layers = nullptr,
-                          const double *hdiv = nullptr, IN *vout = nullptr) {
+                          const BasisNext *bn = nullptr) {
     gnp_system *s = m->sys;
     const int64_t rows = s->n * (int64_t)nrhs;
     const int grid = grid_for(rows, 64);
@@ -205,7 +204,7 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
         const int ge = std::min(grid, resident_blocks<k_encoder_p<G, IN, D, H>>());
         hipLaunchKernelGGL((k_encoder_p<G, IN, D, H>), dim3(ge), dim3(BLOCK), 0, st, rows, nrhs,
                            v, const_cast<double *>(tau), vec, po.W1, po.c1, po.c2, w2, buf(0),
-                           skip, hdiv, vout, s->n);
+                           skip, bn ? *bn : BasisNext{}, s->n);
     }
     for (int l = 0; l < m->L; ++l) {
         const G *X = buf(l);
@@ -227,7 +226,7 @@ static void forward_typed(gnp_model *m, const IN *v, ZT *z, int nrhs, const doub
 template <int D, int H>
 static void forward_dispatch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                              const double *tau, void *a0, void *a1, const int *skip,
-                             hipStream_t st, void *layers, const double *hdiv, void *vout) {
+                             hipStream_t st, void *layers, const BasisNext *bn) {
     if (prec == GNP_F64)
         forward_typed<double, double, double, D, H>(m, (const double *)v, (double *)z, nrhs, tau,
                                                     (double *)a0, (double *)a1, m->theta64,
@@ -235,30 +234,28 @@ static void forward_dispatch(gnp_model *m, gnp_precision prec, const void *v, vo
     else if (prec == GNP_F32)
         forward_typed<float, float, float, D, H>(m, (const float *)v, (float *)z, nrhs, tau,
                                                  (float *)a0, (float *)a1, m->theta32, nullptr,
-                                                 skip, st, (float *)layers, hdiv, (float *)vout);
+                                                 skip, st, (float *)layers, bn);
     else
         forward_typed<uint16_t, float, float, D, H>(m, (const float *)v, (float *)z, nrhs, tau,
                                                     (uint16_t *)a0, (uint16_t *)a1, m->theta32,
                                                     nullptr, skip, st, (uint16_t *)layers,
-                                                    hdiv, (float *)vout);
+                                                    bn);
 }
 
 gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                           const double *tau, void *act0, void *act1, const int *skip,
-                          hipStream_t st, void *layers, const double *hdiv, void *vout) {
-    if (hdiv && (nrhs != 1 || prec == GNP_F64))
-        return fail(GNP_EINVAL, "the encoder normalises only one float32/bfloat16 rhs");
+                          hipStream_t st, void *layers, const BasisNext *bn) {
+    if (bn && (nrhs != 1 || prec == GNP_F64 || !bn->hdiv))
+        return fail(GNP_EINVAL, "the encoder forms basis vectors only for one float32/bfloat16 rhs");
     const int64_t elem = prec == GNP_F64 ? 8 : (prec == GNP_F32 ? 4 : 2);
     if (m->sys->n * (int64_t)nrhs * m->d * elem >= (int64_t)1 << 32)
         return fail(GNP_EINVAL,
                     "an activation block (n * nrhs * d elements) must stay below 4 GiB "
                     "(32-bit gather offsets)");
     if (m->d == 16)
-        forward_dispatch<16, 32>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers, hdiv,
-                                 vout);
+        forward_dispatch<16, 32>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers, bn);
     else
-        forward_dispatch<32, 64>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers, hdiv,
-                                 vout);
+        forward_dispatch<32, 64>(m, prec, v, z, nrhs, tau, act0, act1, skip, st, layers, bn);
     GNP_HIP(hipGetLastError());
     return GNP_OK;
 }

@@ -223,20 +223,25 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
 // ---------------------------------------------------------------------------
 // Persistent encoder for the MFMA paths (float32 / bfloat16 activations):
 // the weights a lane needs are loaded once, and the input of the next tile
-// is requested before the current one is computed.  With hdiv (one
-// right-hand side, inside the solver) the input is the orthogonalised
-// vector w and the network input is the next basis vector v = w / *hdiv,
-// rounded as the basis stores it and written to vout; its tau of Eq. (6) is
-// 1 (v has unit norm), and block 0 publishes that triple for the decoder.
+// is requested before the current one is computed.  With bn.hdiv (one
+// right-hand side, inside the solver) the input is the solver's vector w and
+// the network input is the next basis vector formed here (BasisNext): with
+// bn.V, w - V[:, 0..j] h first, in the solver's correction arithmetic (8
+// lanes per row, lane q owning columns 4q..4q+3, FP64 products summed in
+// column order, then across the 8 lanes by xor 1, 2, 4), then the division
+// by *hdiv.  v is written to bn.vout; its tau of Eq. (6) is 1 (v has unit
+// norm), and block 0 publishes that triple for the decoder.
 // ---------------------------------------------------------------------------
 template <typename G, typename IN, int D, int H>
 __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     int64_t rows, int B, const IN *__restrict__ v, double *__restrict__ tau,
     const float *__restrict__ vec, int64_t oW1, int64_t oc1, int64_t oc2,
     const void *__restrict__ w2, G *__restrict__ E, const int *__restrict__ skip,
-    const double *__restrict__ hdiv, IN *__restrict__ vout, int64_t n) {
+    BasisNext bn, int64_t n) {
     static_assert(sizeof(G) <= 4, "MFMA encoder");
     if (skip && *skip) return;
+    const double *hdiv = bn.hdiv;
+    const bool corr = hdiv && bn.V;  // the second Gram-Schmidt correction here
     const int lane = threadIdx.x % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const float *W1 = vec + oW1, *c1 = vec + oc1, *c2 = vec + oc2;
@@ -272,6 +277,28 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     const int64_t ntiles = (rows + 15) / 16, nw = (int64_t)gridDim.x * (BLOCK / WAVE);
     int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
     IN vn = v[t * 16 + lane % 16 < rows ? t * 16 + lane % 16 : rows - 1];
+    // with the correction: rows t*16 + 8 rho + lane/8 (rho = 0, 1), lane
+    // q = lane % 8 holding basis columns 4q..4q+3 of its row and the row's w;
+    // columns past j are masked below (they may hold an older cycle)
+    const int cq = lane % 8;
+    double hc[4];
+    float4 vq[2];
+    float wq[2];
+    auto load_corr = [&](int64_t tt) {
+#pragma unroll
+        for (int rho = 0; rho < 2; ++rho) {
+            const int64_t r = tt * 16 + 8 * rho + lane / 8;
+            const int64_t rc = r < rows ? r : rows - 1;
+            vq[rho] = *reinterpret_cast<const float4 *>(bn.V + rc * 32 + 4 * cq);
+            wq[rho] = (float)v[rc];
+        }
+    };
+    __shared__ float s_vb[BLOCK / WAVE][16];  // the tile's basis values, by row
+    if (corr) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) hc[a] = 4 * cq + a <= bn.j ? bn.h[4 * cq + a] : 0.0;
+        load_corr(t);
+    }
     // without hdiv: sqrt(n)/tau of every right-hand side (B <= 256) staged in
     // LDS once, so the tile loop waits on no global load but its input
     // prefetch
@@ -292,9 +319,37 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     }
     for (; t < ntiles; t += nw) {
         const int64_t ra = t * 16 + lane % 16;
-        // with hdiv: the basis vector, as the solver's normalisation forms it
-        const IN vc = hdiv ? (IN)((double)vn / div) : vn;
-        if (hdiv && vout && lane < 16 && ra < rows) vout[ra] = vc;
+        IN vc;
+        if (corr) {
+            // w - V h for rows 8 rho + lane/8, then / h_{j+1,j}; exchanged
+            // through LDS into the row-per-lane layout of the network
+#pragma unroll
+            for (int rho = 0; rho < 2; ++rho) {
+                const float qv[4] = {vq[rho].x, vq[rho].y, vq[rho].z, vq[rho].w};
+                double c = 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    c += hc[a] * (4 * cq + a <= bn.j ? (double)qv[a] : 0.0);
+                c += __shfl_xor(c, 1, WAVE);
+                c += __shfl_xor(c, 2, WAVE);
+                c += __shfl_xor(c, 4, WAVE);
+                const IN wn = (IN)((double)wq[rho] - c);
+                const IN vb = (IN)((double)wn / div);
+                const int64_t r = t * 16 + 8 * rho + lane / 8;
+                if (cq == 0) {
+                    s_vb[wv][8 * rho + lane / 8] = vb;
+                    if (bn.vout && r < rows) bn.vout[r] = vb;
+                }
+            }
+            load_corr(t + nw);  // the next tile's rows (clamped past the end)
+            wave_lds_sync();
+            vc = s_vb[wv][lane % 16];
+            wave_lds_sync();  // read before the next tile's writes
+        } else {
+            // with hdiv: the basis vector, as the solver's normalisation forms it
+            vc = hdiv ? (IN)((double)vn / div) : vn;
+            if (hdiv && bn.vout && lane < 16 && ra < rows) bn.vout[ra] = vc;
+        }
         // this tile's scale first, then the next tile's input: waiting for
         // the scale leaves the prefetch in flight
         const double ts = hdiv ? tau1 : s_tau1[(uint32_t)ra % (uint32_t)B];

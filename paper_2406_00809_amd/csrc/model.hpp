@@ -95,17 +95,29 @@ template <typename IN>
 void launch_colnorm(gnp_model *m, const IN *v, int nrhs, double *tau_out, double *partial,
                     unsigned *counter, const int *skip, hipStream_t st);
 
+// The solver's next basis vector, formed by the encoder as it reads w (one
+// right-hand side, float32 basis): with V given, the second Gram-Schmidt
+// correction first, w - V[:, 0..j] h (basis pitch 32, the arithmetic of the
+// solver's correction pass), then v = (that) / *hdiv, rounded as the basis
+// stores it and written to vout.  The network takes v with tau = 1 (v has
+// unit norm) and the encoder writes that tau triple.
+struct BasisNext {
+    const double *hdiv = nullptr;  // h_{j+1,j}
+    float *vout = nullptr;         // v, the solver's contiguous copy
+    const float *V = nullptr;      // basis (pitch 32); nullptr: w is already final
+    const double *h = nullptr;     // correction coefficients h[0..j]
+    int j = 0;
+};
+
 // z = M(v) given precomputed tau triples.  act0/act1: activation buffers.
 // When layers != nullptr, X_0 (encoder output) and every layer output X_l
 // are kept in block l of layers ((L+1) blocks of n * nrhs * d activations)
-// instead of ping-ponging between act0 and act1.  With hdiv (one
-// float32/bfloat16 right-hand side, inside the solver) v is the
-// orthogonalised vector w: the encoder forms the next basis vector w / *hdiv
-// (stored to vout when given) and feeds it to the network with tau = 1,
-// writing that triple to tau.
+// instead of ping-ponging between act0 and act1.  With bn (one
+// float32/bfloat16 right-hand side, inside the solver) v is the solver's
+// vector w and the encoder forms the next basis vector itself (BasisNext).
 gnp_status forward_launch(gnp_model *m, gnp_precision prec, const void *v, void *z, int nrhs,
                           const double *tau, void *act0, void *act1, const int *skip,
-                          hipStream_t st, void *layers = nullptr, const double *hdiv = nullptr,
-                          void *vout = nullptr);
+                          hipStream_t st, void *layers = nullptr,
+                          const struct BasisNext *bn = nullptr);
 
 }  // namespace gnp

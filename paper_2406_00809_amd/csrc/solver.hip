@@ -668,8 +668,11 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     const int *skip = &c->ctl->cycle_done;
     // the basis vector v_j (j >= 1) = w / h_{j,j-1}: formed by the encoder of
     // a float32/bfloat16 network as it reads w (it also stores v_j to vcur),
-    // else by its own kernel at the end of step j - 1
+    // else by its own kernel at the end of step j - 1; with a basis of pitch
+    // 32 that encoder also applies step j - 1's second correction w -= V h2,
+    // so that pass is not launched
     const bool v_in_encoder = model && c->prec != GNP_F64;
+    const bool corr_in_encoder = v_in_encoder && MP == 32;
     hipLaunchKernelGGL((k_normalize<KT, double>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, vcur,
                        c->ctl, 1, Bat{});
     if (model)
@@ -678,10 +681,19 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     for (int j = 0; j < nsteps; ++j) {
         KT *zj = model ? Z + (int64_t)j * n : vcur;
         const bool fuse = v_in_encoder && j > 0;
+        BasisNext bn;
+        if (fuse) {
+            bn.hdiv = &c->ctl->hnext;
+            bn.vout = (float *)vcur;
+            if (corr_in_encoder) {
+                bn.V = (const float *)V;
+                bn.h = c->h2;
+                bn.j = j - 1;
+            }
+        }
         if (model)
             GNP_TRY(forward_launch(model, c->prec, fuse ? w : vcur, zj, 1, c->tau, c->act[0],
-                                   c->act[1], skip, st, nullptr,
-                                   fuse ? &c->ctl->hnext : nullptr, fuse ? vcur : nullptr));
+                                   c->act[1], skip, st, nullptr, fuse ? &bn : nullptr));
         spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st, 1, 1, 0, 0,
                                 s->max_row);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
@@ -695,9 +707,10 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
         hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
                            c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, Bat{});
-        hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
-                           (const double *)c->h2, c->partial, pstride, (const Ctl *)c->ctl,
-                           Bat{}, (const KT *)nullptr);
+        if (!corr_in_encoder)
+            hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j,
+                               w, (const double *)c->h2, c->partial, pstride,
+                               (const Ctl *)c->ctl, Bat{}, (const KT *)nullptr);
         if (!v_in_encoder) {
             hipLaunchKernelGGL((k_normalize<KT, KT>), dim3(sg), dim3(BLOCK), 0, st, n,
                                (const KT *)w, vcur, c->ctl, 0, Bat{});
