@@ -47,6 +47,8 @@ def lib():
             build()
         L = C.CDLL(LIB)
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
+        L.or_set_num_threads.restype = None
         L.or_spmm.argtypes = [C.c_int64, I32P, I32P, F64P, C.c_int, F64P, F64P]
         L.or_gamma.argtypes = [C.c_int64, I32P, I32P, F64P]
         L.or_gamma.restype = C.c_double
@@ -90,6 +92,11 @@ def _c64(a):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().or_set_num_threads(int(k))
 
 
 # --- CSR ---------------------------------------------------------------------

@@ -55,6 +55,17 @@ OR_API int or_num_threads(void)
 #endif
 }
 
+/* Set that number (timing with one thread and with all of them); results do
+   not depend on it (fixed-size chunks, summed in index order). */
+OR_API void or_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sparse matrix basics                                                     */
 /* ------------------------------------------------------------------------ */
