@@ -340,6 +340,11 @@ __global__ __launch_bounds__(BLOCK) void k_dec_bwd_mfma(int64_t rows, int B,
 // Res-GCONV backward, part 1 (Eq. (5), Y = ReLU(X U + A-hat X W)):
 // recompute T = A-hat X, dP = dY [Y > 0], store G = dP W^T and Hx = dP U^T,
 // and accumulate dU += X^T dP, dW += T^T dP.
+// When B is a multiple of 16 (the training batches), the 16 rows of a tile
+// are right-hand sides of one node and share its CSR row: the row pointers
+// are fetched two tiles ahead and the row's first NE entries one tile ahead,
+// so a tile costs one memory round trip (its own rows and all neighbour rows
+// in flight together).  Either way T is summed in CSR order.
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_layer_bwd1_mfma(
@@ -352,7 +357,8 @@ __global__ __launch_bounds__(BLOCK) void k_layer_bwd1_mfma(
     constexpr int SM = 4 * WAVE_F > D * D ? 4 * WAVE_F : D * D;
     __shared__ float smem[SM];
     __shared__ float Us[D * LX], Ws[D * LX];
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     float *Xs = smem + wv * WAVE_F, *Ts = Xs + 16 * LX, *Ps = Ts + 16 * LX;
     for (int e = threadIdx.x; e < D * D; e += BLOCK) {
         Us[(e / D) * LX + e % D] = th[oU + e];
@@ -365,30 +371,19 @@ __global__ __launch_bounds__(BLOCK) void k_layer_bwd1_mfma(
 #pragma unroll
         for (int b = 0; b < D / 16; ++b) gU[a][b] = gW[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int64_t ntiles = (rows + 15) / 16, nw = (int64_t)gridDim.x * (BLOCK / WAVE);
-    for (int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv; t < ntiles; t += nw) {
-        const int64_t r0 = t * 16;
-        {
-            const int rl = lane / 4, q = lane % 4;
-            const int64_t r = r0 + rl;
-            float tv[D / 4], xv[D / 4], yv[D / 4], gv[D / 4];
+    const int rl = lane / 4, q = lane % 4;
+    // the tile's rows staged in LDS: products with the weights, stores, and
+    // the weight-gradient outer products
+    auto stage = [&](const float (&xv)[D / 4], const float (&tv)[D / 4], const float (&yv)[D / 4],
+                     const float (&gv)[D / 4]) {
 #pragma unroll
-            for (int e = 0; e < D / 4; ++e) tv[e] = xv[e] = yv[e] = gv[e] = 0.f;
-            if (r < rows) {
-                const int64_t i = (B == 1) ? r : r / B;
-                const int b = (int)(r - i * B);
-                load_feats<float, D / 4>(X + r * D + q * (D / 4), xv);
-                load_feats<float, D / 4>(Y + r * D + q * (D / 4), yv);
-                load_feats<float, D / 4>(dY + r * D + q * (D / 4), gv);
-                gather_rows<float, D / 4, 4>(ci, ahat, rp[i], rp[i + 1], X, (uint32_t)B,
-                                             (uint32_t)b, q, tv);
-            }
-#pragma unroll
-            for (int e = 0; e < D / 4; ++e) {
-                Xs[rl * LX + q * (D / 4) + e] = xv[e];
-                Ts[rl * LX + q * (D / 4) + e] = tv[e];
-                Ps[rl * LX + q * (D / 4) + e] = yv[e] > 0.f ? gv[e] : 0.f;
-            }
+        for (int e = 0; e < D / 4; ++e) {
+            Xs[rl * LX + q * (D / 4) + e] = xv[e];
+            Ts[rl * LX + q * (D / 4) + e] = tv[e];
+            Ps[rl * LX + q * (D / 4) + e] = yv[e] > 0.f ? gv[e] : 0.f;
         }
+    };
+    auto finish = [&](int64_t r0) {
         wave_lds_sync();
         f32x4 o[D / 16];
         const int64_t r = r0 + lane % 16;
@@ -409,6 +404,91 @@ __global__ __launch_bounds__(BLOCK) void k_layer_bwd1_mfma(
         outer_acc<D, D>(Xs, LX, Ps, LX, gU, lane);
         outer_acc<D, D>(Ts, LX, Ps, LX, gW, lane);
         wave_lds_sync();
+    };
+    int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
+    if (B % 16 == 0) {
+        constexpr int NE = 8;  // entries of the shared CSR row prefetched per tile
+        // node of tile tt (clamped past the end: loads stay in range, results unused)
+        auto node = [&](int64_t tt) -> int64_t { return (tt < ntiles ? tt : ntiles - 1) * 16 / B; };
+        // entries rs.. of a row ending at re: column and weight, 0 past the end
+        auto entries = [&](int32_t rs, int32_t re, int32_t (&c)[NE], float (&w)[NE]) {
+#pragma unroll
+            for (int u = 0; u < NE; ++u) {
+                const int32_t k = rs + u;
+                const int32_t kc = k < re ? k : (re > 0 ? re - 1 : 0);
+                c[u] = ci[kc];
+                w[u] = k < re ? ahat[kc] : 0.f;
+            }
+        };
+        int64_t i0 = node(t);
+        int32_t rs0 = rp[i0], re0 = rp[i0 + 1];
+        int32_t c0[NE];
+        float a0[NE];
+        entries(rs0, re0, c0, a0);
+        const int64_t i1 = node(t + nw);
+        int32_t rs1 = rp[i1], re1 = rp[i1 + 1];
+        for (; t < ntiles; t += nw) {
+            // next tile's entries and the row pointers of the one after, in
+            // flight with this tile's loads
+            int32_t c1[NE];
+            float a1[NE];
+            entries(rs1, re1, c1, a1);
+            const int64_t i2 = node(t + 2 * nw);
+            const int32_t rs2 = rp[i2], re2 = rp[i2 + 1];
+            const int64_t r0 = t * 16;
+            {
+                const int64_t r = r0 + rl;  // rows is a multiple of 16 here
+                const uint32_t b = (uint32_t)(r % B);
+                float tv[D / 4], xv[D / 4], yv[D / 4], gv[D / 4];
+                load_feats<float, D / 4>(X + r * D + q * (D / 4), xv);
+                load_feats<float, D / 4>(Y + r * D + q * (D / 4), yv);
+                load_feats<float, D / 4>(dY + r * D + q * (D / 4), gv);
+                float nv[NE][D / 4];
+#pragma unroll
+                for (int u = 0; u < NE; ++u)
+                    load_feats<float, D / 4>(X + ((int64_t)c0[u] * B + b) * D + q * (D / 4), nv[u]);
+#pragma unroll
+                for (int e = 0; e < D / 4; ++e) tv[e] = 0.f;
+#pragma unroll
+                for (int u = 0; u < NE; ++u)
+#pragma unroll
+                    for (int e = 0; e < D / 4; ++e) tv[e] += a0[u] * nv[u][e];
+                if (re0 - rs0 > NE)  // the rest of a longer row, in order
+                    gather_rows<float, D / 4, 4>(ci, ahat, rs0 + NE, re0, X, (uint32_t)B, b, q, tv);
+                stage(xv, tv, yv, gv);
+            }
+            finish(r0);
+#pragma unroll
+            for (int u = 0; u < NE; ++u) {
+                c0[u] = c1[u];
+                a0[u] = a1[u];
+            }
+            rs0 = rs1;
+            re0 = re1;
+            rs1 = rs2;
+            re1 = re2;
+        }
+    } else {
+        for (; t < ntiles; t += nw) {
+            const int64_t r0 = t * 16;
+            {
+                const int64_t r = r0 + rl;
+                float tv[D / 4], xv[D / 4], yv[D / 4], gv[D / 4];
+#pragma unroll
+                for (int e = 0; e < D / 4; ++e) tv[e] = xv[e] = yv[e] = gv[e] = 0.f;
+                if (r < rows) {
+                    const int64_t i = (B == 1) ? r : r / B;
+                    const int b = (int)(r - i * B);
+                    load_feats<float, D / 4>(X + r * D + q * (D / 4), xv);
+                    load_feats<float, D / 4>(Y + r * D + q * (D / 4), yv);
+                    load_feats<float, D / 4>(dY + r * D + q * (D / 4), gv);
+                    gather_rows<float, D / 4, 4>(ci, ahat, rp[i], rp[i + 1], X, (uint32_t)B,
+                                                 (uint32_t)b, q, tv);
+                }
+                stage(xv, tv, yv, gv);
+            }
+            finish(r0);
+        }
     }
     __syncthreads();
     double *gp = gpart + (int64_t)blockIdx.x * np;

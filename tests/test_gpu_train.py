@@ -41,6 +41,11 @@ GRAD_CASES = {
     "ragged_laplace2d_13_d16": (lambda: I.laplace2d(13), 2, 16, 32, 3),
     # fewer rows than one tile
     "tiny_laplace2d_3_d32": (lambda: I.laplace2d(3), 1, 32, 64, 1),
+    # batches that are multiples of 16 (a tile = right-hand sides of one node)
+    "laplace2d_16_d16_b16": (lambda: I.laplace2d(16), 2, 16, 32, 16),
+    # ... with rows longer than the 8 prefetched entries
+    "powerlaw_3000_d32_b32": (lambda: I.powerlaw_random(3000, seed_structure=3, seed_values=4),
+                              2, 32, 64, 32),
 }
 
 
