@@ -44,6 +44,9 @@ CASES = {
     "powerlaw_4000_d32_nb3": (lambda: I.powerlaw_random(4000, seed_structure=11,
                                                         seed_values=12), (4, 32, 64), 3, 30),
     "laplace2d_30_d16_nb1": (lambda: I.laplace2d(30), (3, 16, 32), 1, 10),
+    # restart 40: basis pitch 64, where single solves launch the third
+    # Gram-Schmidt pass themselves
+    "convdiff3d_12_d32_nb4_m40": (lambda: I.convdiff3d(12), (4, 32, 64), 4, 40),
 }
 
 

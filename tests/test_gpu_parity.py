@@ -211,36 +211,39 @@ def test_fgmres_identity_f64_matches_oracle(api, m):
     assert true <= 1e-8 and abs(true - info["rel_res_true"]) <= 1e-6 * true
 
 
-def test_fgmres_c1_trained_f64_matches_oracle(api):
-    """C1: 2D Laplacian 32x32, oracle-trained GNP (L=4,d=16,h=32), FGMRES(10)."""
+@pytest.mark.parametrize("m", [10, 40])
+def test_fgmres_c1_trained_f64_matches_oracle(api, m):
+    """C1: 2D Laplacian 32x32, oracle-trained GNP (L=4,d=16,h=32), FGMRES(10)
+    (and FGMRES(40): a basis pitch of 64)."""
     A = I.laplace2d(32)
     th = np.load(os.path.join(GOLD, "c1_gnp_oracle_trained.npy"))
     S = api.System(A)
     ref = O.System(A)
     M = api.Model(S, 4, 16, 32, th)
     b = I.rhs_normal(A.n, 0)
-    x, info, hist = api.fgmres_solve(S, _dev(b, _kdt("f64")), M, m=10, rtol=1e-8,
+    x, info, hist = api.fgmres_solve(S, _dev(b, _kdt("f64")), M, m=m, rtol=1e-8,
                                      maxiters=3000, prec="f64")
-    r = O.fgmres(ref, b, 10, 1e-8, 3000, M="gnp", theta=th, arch=(4, 16, 32), ortho=O.CGS2)
+    r = O.fgmres(ref, b, m, 1e-8, 3000, M="gnp", theta=th, arch=(4, 16, 32), ortho=O.CGS2)
     print("gpu", info, "oracle", r["info"])
     assert info["converged"] == 1 and r["info"]["converged"] == 1
     assert _iters_close(info["iters"], r["info"]["iters"])
-    n0 = min(len(hist), len(r["hist"]), 11)
+    n0 = min(len(hist), len(r["hist"]), m + 1)
     np.testing.assert_allclose(hist[:n0], r["hist"][:n0], rtol=1e-8)
 
 
+@pytest.mark.parametrize("m", [10, 40])  # 40: basis pitch 64, the separate third pass
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_fgmres_c1_trained_reduced_precision(api, prec):
+def test_fgmres_c1_trained_reduced_precision(api, prec, m):
     A = I.laplace2d(32)
     th = np.load(os.path.join(GOLD, "c1_gnp_oracle_trained.npy"))
     S = api.System(A)
     ref = O.System(A)
     M = api.Model(S, 4, 16, 32, th)
     b = I.rhs_normal(A.n, 0)
-    x, info, hist = api.fgmres_solve(S, _dev(b, _kdt("f64")), M, m=10, rtol=1e-8,
+    x, info, hist = api.fgmres_solve(S, _dev(b, _kdt("f64")), M, m=m, rtol=1e-8,
                                      maxiters=3000, prec=prec)
-    r = O.fgmres(ref, b, 10, 1e-8, 3000, M="gnp", theta=th, arch=(4, 16, 32), ortho=O.CGS2)
-    print(prec, "gpu", info, "oracle", r["info"])
+    r = O.fgmres(ref, b, m, 1e-8, 3000, M="gnp", theta=th, arch=(4, 16, 32), ortho=O.CGS2)
+    print(prec, m, "gpu", info, "oracle", r["info"])
     xs = x.cpu().numpy()
     true = np.linalg.norm(b - ref.A.to_scipy() @ xs) / np.linalg.norm(b)
     assert info["converged"] == 1 and true <= 1e-8
