@@ -1,10 +1,13 @@
 // Restarted flexible GMRES (Algorithm 1) with the network as nonlinear right
 // preconditioner.  Per Arnoldi step j the stream holds: z_j = M(v_j), the
-// SpMV w = A z_j, three classical Gram-Schmidt passes (dots; update + dots;
-// update + norm, i.e. CGS applied twice with float64 inner products), the
-// Givens update of the Hessenberg column on the device, and the
-// normalisation v_{j+1} = w / h_{j+1,j} with the float64 norm that the next
-// network input needs for its scaling (Eq. (6)).
+// SpMV w = A z_j, classical Gram-Schmidt applied twice with float64 inner
+// products (pass 0: dots; pass 1: update + dots + ||w||^2; pass 2: update),
+// the Givens update of the Hessenberg column on the device (its finaliser
+// also forms h_{j+1,j} from pass 1's sums), and the normalisation
+// v_{j+1} = w / h_{j+1,j}.  With a float32/bfloat16 network the next step's
+// encoder does the normalisation, and with a basis pitch of 32 also pass 2,
+// as it reads w; the network takes tau = 1 for every basis vector (unit norm,
+// Eq. (6)).
 //
 // Layout: the Arnoldi basis is stored row-interleaved, V[i * MP + k]
 // (MP = m + 1 rounded up to a multiple of 32), so that the j + 1 basis
@@ -15,7 +18,8 @@
 //
 // Reductions are deterministic: each block writes its partial sums, and a
 // one-block finalize kernel adds the partials in block order (lanes over
-// columns, wavefronts over block subsets, eight independent loads per lane).
+// columns, wavefronts over block subsets, up to 64 independent loads per lane in
+// one round).
 // The host synchronises once per restart cycle; every kernel of a step exits
 // at entry once the device-side control block says the cycle is over.
 #include <math.h>
