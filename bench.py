@@ -397,6 +397,15 @@ def main():
         extra["no_preconditioner"] = {"solves_per_s": rate, "iters": inf3["iters"],
                                       "rel_res_true": inf3["rel_res_true"]}
 
+        def jacobi():
+            x.zero_()
+            return api.fgmres_solve_jacobi(S, b, x=x, m=m, rtol=1e-8, maxiters=args.maxiters,
+                                           prec="f32", want_hist=False)[1]
+
+        rate, inf5 = median_rate(jacobi)
+        extra["jacobi_preconditioner"] = {"solves_per_s": rate, "iters": inf5["iters"],
+                                          "rel_res_true": inf5["rel_res_true"]}
+
         # 32 right-hand sides b ~ N(0, I): float32 network one solve at a time,
         # against the bfloat16 network served with 32 concurrent slots
         nb = 32

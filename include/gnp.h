@@ -188,6 +188,18 @@ GNP_API gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const double 
                                 gnp_precision prec, double *hist, gnp_solve_info *info,
                                 void *hip_stream);
 
+/* fgmres_solve with the Jacobi preconditioner M = D^{-1}, D the diagonal of
+ * the system matrix (prescaled when the system is): the simple baseline the
+ * paper compares the network against (Sec. 3, "Compared methods").  Each
+ * Arnoldi step applies z_j = D^{-1} v_j in float64 and rounds to the Krylov
+ * precision; everything else is as in fgmres_solve.  D^{-1} is formed on the
+ * device on first use and kept with the system.
+ * prec: GNP_F32 or GNP_F64.  Errors: as fgmres_solve, plus GNP_EINVAL when a
+ * row has no nonzero diagonal entry or for another precision. */
+GNP_API gnp_status fgmres_solve_jacobi(gnp_system *sys, const double *b_dev, double *x_dev,
+                                       int m, double rtol, int maxiters, gnp_precision prec,
+                                       double *hist, gnp_solve_info *info, void *hip_stream);
+
 
 /* Solve A x_k = b_k for nrhs right-hand sides at once (each one exactly as
  * fgmres_solve would, step for step), with one network application per

@@ -178,6 +178,7 @@ struct gnp_system {
     unsigned *counters = nullptr;                // tickets for last-block reductions
     double *scratch = nullptr;                   // small reduction scratch
     int nscratch = 0;
+    double *dinv64 = nullptr;                    // 1 / a_ii (Jacobi preconditioner), made on first use
     void *solve_cache = nullptr;                 // FGMRES workspace of fgmres_solve
     void *batch_cache = nullptr;                 // workspace of fgmres_solve_batch
 };

@@ -187,6 +187,34 @@ __global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *
 }
 
 // ---------------------------------------------------------------------------
+// Jacobi preconditioner (the weak baseline of Sec. 3, "Compared methods"):
+// dinv = 1 / a_ii of the system matrix (prescaled when the system is), then
+// z = dinv * v per Arnoldi step.  flag is set when a row has no nonzero
+// diagonal entry.
+// ---------------------------------------------------------------------------
+__global__ void k_diag_inv(int64_t n, const int32_t *__restrict__ rp,
+                           const int32_t *__restrict__ ci, const double *__restrict__ val,
+                           double *__restrict__ dinv, int *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) d = val[k];
+    if (d == 0.0) atomicOr(flag, 1);
+    dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+}
+
+template <typename KT>
+__global__ __launch_bounds__(BLOCK) void k_jacobi(int64_t n, const double *__restrict__ dinv,
+                                                  const KT *__restrict__ v, KT *__restrict__ z,
+                                                  const Ctl *ctl) {
+    if (ctl->cycle_done) return;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BLOCK)
+        z[i] = (KT)(dinv[i] * (double)v[i]);
+}
+
+// ---------------------------------------------------------------------------
 // v = src / div into vcur (contiguous), div = beta (cycle start) or
 // h_{j+1,j}.  The basis column of v is written by the next step's first
 // Gram-Schmidt pass, which reads that row of the basis anyway.  (With a
@@ -677,13 +705,16 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     // so that pass is not launched
     const bool v_in_encoder = model && c->prec != GNP_F64;
     const bool corr_in_encoder = v_in_encoder && MP == 32;
+    // Jacobi: z_j = D^{-1} v_j; with any preconditioner z_j is kept in Z
+    const bool jac = !model && c->precond == PRECOND_JACOBI;
+    const bool flex = model || jac;
     hipLaunchKernelGGL((k_normalize<KT, double>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, vcur,
                        c->ctl, 1, Bat{});
     if (model)
         hipLaunchKernelGGL(k_unit_tau, dim3(1), dim3(WAVE), 0, st, n, c->tau, c->ctl,
                            (int *)nullptr);
     for (int j = 0; j < nsteps; ++j) {
-        KT *zj = model ? Z + (int64_t)j * n : vcur;
+        KT *zj = flex ? Z + (int64_t)j * n : vcur;
         const bool fuse = v_in_encoder && j > 0;
         BasisNext bn;
         if (fuse) {
@@ -698,6 +729,10 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
         if (model)
             GNP_TRY(forward_launch(model, c->prec, fuse ? w : vcur, zj, 1, c->tau, c->act[0],
                                    c->act[1], skip, st, nullptr, fuse ? &bn : nullptr));
+        else if (jac)
+            hipLaunchKernelGGL((k_jacobi<KT>), dim3(sg), dim3(BLOCK), 0, st, n,
+                               (const double *)s->dinv64, (const KT *)vcur, zj,
+                               (const Ctl *)c->ctl);
         spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st, 1, 1, 0, 0,
                                 s->max_row);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
@@ -724,7 +759,7 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
         }
     }
     hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(BLOCK), 0, st, c->ctl, c->H, c->g, c->y, Bat{});
-    if (model)
+    if (flex)
         hipLaunchKernelGGL((k_update_x<KT, MP, false>), dim3(sg), dim3(BLOCK), 0, st, n,
                            (const KT *)Z, c->y, c->ctl, x);
     else
@@ -1086,6 +1121,59 @@ extern "C" gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const doub
     c->prec = prec;
     return solve_run(c, model, b_dev, x_dev, m, rtol, maxiters, hist, info,
                      (hipStream_t)hip_stream);
+}
+
+// D^{-1} of the system, made once (GNP_EINVAL for a zero or missing diagonal entry)
+static gnp_status system_dinv(gnp_system *s, hipStream_t st) {
+    if (s->dinv64) return GNP_OK;
+    double *d = nullptr;
+    int *flag = nullptr;
+    GNP_HIP(hipMalloc(&d, sizeof(double) * s->n));
+    if (hipMalloc(&flag, sizeof(int)) != hipSuccess) {
+        (void)hipFree(d);
+        return fail(GNP_ENOMEM, "hipMalloc failed");
+    }
+    int h = 0;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_diag_inv, dim3(grid_for(s->n, BLOCK)), dim3(BLOCK), 0, st, s->n, s->rp,
+                           s->ci, (const double *)s->val64, d, flag);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(flag);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return check_hip(e, "Jacobi diagonal");
+    }
+    if (h) {
+        (void)hipFree(d);
+        return fail(GNP_EINVAL, "Jacobi needs a nonzero diagonal entry in every row");
+    }
+    s->dinv64 = d;
+    return GNP_OK;
+}
+
+extern "C" gnp_status fgmres_solve_jacobi(gnp_system *sys, const double *b_dev, double *x_dev,
+                                          int m, double rtol, int maxiters, gnp_precision prec,
+                                          double *hist, gnp_solve_info *info, void *hip_stream) {
+    if (!sys || !b_dev || !x_dev) return fail(GNP_EINVAL, "null argument");
+    if (m < 1 || m > 255) return fail(GNP_EINVAL, "m must be in [1, 255]");
+    if (!(rtol > 0.0)) return fail(GNP_EINVAL, "rtol must be > 0");
+    if (maxiters < 1) return fail(GNP_EINVAL, "maxiters must be >= 1");
+    if (prec != GNP_F32 && prec != GNP_F64)
+        return fail(GNP_EINVAL, "the Jacobi solve runs in float32 or float64");
+    hipStream_t st = (hipStream_t)hip_stream;
+    GNP_TRY(system_dinv(sys, st));
+    if (!sys->solve_cache) sys->solve_cache = new SolveCtx();
+    SolveCtx *c = (SolveCtx *)sys->solve_cache;
+    GNP_TRY(solve_ctx_prepare(c, sys, m, maxiters, prec, 0));
+    c->prec = prec;
+    c->precond = PRECOND_JACOBI;
+    const gnp_status r = solve_run(c, nullptr, b_dev, x_dev, m, rtol, maxiters, hist, info, st);
+    c->precond = PRECOND_MODEL;
+    return r;
 }
 
 extern "C" gnp_status fgmres_solve_batch(gnp_system *sys, gnp_model *model, const double *b_dev,

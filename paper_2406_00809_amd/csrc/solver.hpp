@@ -35,8 +35,12 @@ struct Bat {
     int vstep = 1;      // stride of the network input vector (nrhs when packed [n][nrhs])
 };
 
+// Preconditioner of a solve besides the network (which is passed as a model)
+enum PrecondKind { PRECOND_MODEL = 0, PRECOND_JACOBI = 1 };
+
 struct SolveCtx {
     gnp_system *sys = nullptr;
+    int precond = PRECOND_MODEL;  // PRECOND_JACOBI: z_j = D^{-1} v_j (sys->dinv64)
     int m = 0;
     int mp = 32;            // row pitch of the interleaved basis
     int maxiters_cap = 0;

@@ -183,7 +183,7 @@ static void sys_free(gnp_system *s) {
     if (!s) return;
     void *ptrs[] = {s->rp,     s->ci,      s->val64,  s->val32,   s->ahat64,  s->ahat32,
                     s->trp,    s->tci,     s->tval64, s->tval32,  s->tahat64, s->tahat32,
-                    s->ahat16,   s->counters, s->scratch};
+                    s->ahat16,   s->counters, s->scratch, s->dinv64};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     solve_cache_free(s->solve_cache);

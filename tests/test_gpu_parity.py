@@ -270,3 +270,65 @@ def test_fgmres_edge_cases(api):
     bad[3] = float("nan")
     with pytest.raises(GNPError):
         api.fgmres_solve(S, bad, None, m=5, rtol=1e-8, maxiters=10, prec="f32")
+
+
+# ---------------------------------------------------------------------------
+# Jacobi preconditioner (Sec. 3, "Compared methods"): M = D^{-1} of the
+# prescaled matrix, against the oracle's FGMRES with the same diagonal M
+# ---------------------------------------------------------------------------
+JACOBI_CASES = {
+    # diagonal +-10^U(-4, 0): Jacobi changes the iteration a lot
+    "powerlaw_3000": lambda: I.powerlaw_random(3000, seed_structure=13, seed_values=14),
+    "convdiff3d_10": lambda: I.convdiff3d(10),
+}
+
+
+@pytest.mark.parametrize("mat", list(JACOBI_CASES))
+def test_fgmres_jacobi_f64_matches_oracle(api, mat):
+    A = JACOBI_CASES[mat]()
+    S = api.System(A)
+    ref = O.System(A)
+    dinv = 1.0 / ref.A.to_scipy().diagonal()
+    b = I.rhs_normal(A.n, 7)
+    m, maxit = 30, 90
+    x, info, hist = api.fgmres_solve_jacobi(S, _dev(b, _kdt("f64")), m=m, rtol=1e-8,
+                                            maxiters=maxit, prec="f64")
+    r = O.fgmres(ref, b, m, 1e-8, maxit, M="diag", mat=dinv, ortho=O.CGS2)
+    print(mat, "gpu", info, "oracle", r["info"])
+    assert info["converged"] == r["info"]["converged"]
+    assert _iters_close(info["iters"], r["info"]["iters"])
+    n0 = min(len(hist), len(r["hist"]), m + 1)
+    np.testing.assert_allclose(hist[:n0], r["hist"][:n0], rtol=1e-8)
+    xs = x.cpu().numpy()
+    true = np.linalg.norm(b - ref.A.to_scipy() @ xs) / np.linalg.norm(b)
+    assert abs(true - info["rel_res_true"]) <= 1e-6 * true
+
+
+def test_fgmres_jacobi_f32(api):
+    A = I.convdiff3d(10)
+    S = api.System(A)
+    ref = O.System(A)
+    dinv = 1.0 / ref.A.to_scipy().diagonal()
+    b = I.rhs_normal(A.n, 8)
+    x, info, _ = api.fgmres_solve_jacobi(S, _dev(b, _kdt("f64")), m=30, rtol=1e-8,
+                                         maxiters=500, prec="f32")
+    r = O.fgmres(ref, b, 30, 1e-8, 500, M="diag", mat=dinv, ortho=O.CGS2)
+    print("gpu", info, "oracle", r["info"])
+    xs = x.cpu().numpy()
+    true = np.linalg.norm(b - ref.A.to_scipy() @ xs) / np.linalg.norm(b)
+    assert info["converged"] == 1 and true <= 1e-8
+    assert _iters_close(info["iters"], r["info"]["iters"])
+
+
+def test_fgmres_jacobi_errors(api):
+    from paper_2406_00809_amd._lib import GNPError
+    # a zero diagonal entry: [[0, 1], [1, 2]]
+    A = I.CSR(2, np.array([0, 1, 3], dtype=np.int32), np.array([1, 0, 1], dtype=np.int32),
+              np.array([1.0, 1.0, 2.0]), "zero_diag")
+    S = api.System(A)
+    b = _dev(np.ones(2), _kdt("f64"))
+    with pytest.raises(GNPError):
+        api.fgmres_solve_jacobi(S, b, m=2, rtol=1e-8, maxiters=4, prec="f64")
+    S2 = api.System(I.laplace2d(4))
+    with pytest.raises(GNPError):
+        api.fgmres_solve_jacobi(S2, _dev(np.ones(16), _kdt("f64")), prec="bf16")
