@@ -19,7 +19,7 @@ I32P = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 F64P = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 U32P = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 
-OR_M_IDENTITY, OR_M_GNP, OR_M_DENSE, OR_M_DIAG = 0, 1, 2, 3
+OR_M_IDENTITY, OR_M_GNP, OR_M_DENSE, OR_M_DIAG, OR_M_GMRES = 0, 1, 2, 3, 4
 MGS, CGS2 = 0, 1
 
 
@@ -27,7 +27,9 @@ class Precond(C.Structure):
     _fields_ = [("kind", C.c_int),
                 ("rp", C.c_void_p), ("ci", C.c_void_p), ("ahat", C.c_void_p),
                 ("L", C.c_int), ("d", C.c_int), ("h", C.c_int),
-                ("theta", C.c_void_p), ("mat", C.c_void_p)]
+                ("theta", C.c_void_p), ("mat", C.c_void_p),
+                ("aval", C.c_void_p), ("inner_k", C.c_int), ("inner_tol", C.c_double),
+                ("inner_ortho", C.c_int)]
 
 
 class Info(C.Structure):
@@ -283,10 +285,13 @@ def train(S: System, L, d, h, theta0, steps, B, lr=1e-3, seed=2, x_fixed=None,
 # --- FGMRES ------------------------------------------------------------------
 
 def fgmres(S: System, b, m, rtol, maxiters, M="identity", theta=None, arch=None, mat=None,
-           ortho=CGS2, x0=None, dump=False):
+           ortho=CGS2, x0=None, dump=False, inner=None):
     """Algorithm 1 with the stopping readings of oracle.c.
 
-    M: "identity" | "gnp" (theta, arch=(L,d,h)) | "dense" (mat n x n) | "diag" (mat n).
+    M: "identity" | "gnp" (theta, arch=(L,d,h)) | "dense" (mat n x n) | "diag" (mat n)
+    | "gmres" (inner=(k, tol): inner-outer GMRES, z = one cycle of at most k
+    unpreconditioned GMRES steps on A z = v from 0, ended at residual tol ||v||;
+    the inner solve orthogonalises with `ortho` too).
     Returns dict with x, hist, info (and V, Z, H, k if dump).
     """
     n = S.n
@@ -309,6 +314,15 @@ def fgmres(S: System, b, m, rtol, maxiters, M="identity", theta=None, arch=None,
         mm = _c64(mat)
         keep += [mm]
         pc.mat = mm.ctypes.data
+    elif M == "gmres":
+        k, tol = inner
+        if not 1 <= int(k) <= 1000:
+            raise ValueError("inner k must be in [1, 1000]")
+        av = _c64(S.A.val)
+        keep += [av]
+        pc.kind = OR_M_GMRES
+        pc.rp, pc.ci, pc.aval = S.A.rowptr.ctypes.data, S.A.colind.ctypes.data, av.ctypes.data
+        pc.inner_k, pc.inner_tol, pc.inner_ortho = int(k), float(tol), int(ortho)
     else:
         raise ValueError(M)
     hist = np.full(maxiters + 1, np.nan)

@@ -549,7 +549,7 @@ OR_API int or_train(int64_t n, const int32_t *rp, const int32_t *ci, const doubl
 /* FGMRES with a nonlinear right preconditioner (Algorithm 1, Sec. 2.1)     */
 /* ------------------------------------------------------------------------ */
 
-enum { OR_M_IDENTITY = 0, OR_M_GNP = 1, OR_M_DENSE = 2, OR_M_DIAG = 3 };
+enum { OR_M_IDENTITY = 0, OR_M_GNP = 1, OR_M_DENSE = 2, OR_M_DIAG = 3, OR_M_GMRES = 4 };
 
 typedef struct {
     int kind;
@@ -560,12 +560,25 @@ typedef struct {
     const double *theta;
     /* DENSE: n x n row-major matrix; DIAG: n entries */
     const double *mat;
+    /* GMRES (inner-outer GMRES, Sec. 3 "Compared methods"): z = one cycle of
+       at most inner_k unpreconditioned Arnoldi steps on A z = v from z = 0,
+       ended early once the Givens estimate is <= inner_tol ||v||; A is
+       (rp, ci, aval) */
+    const double *aval;
+    int inner_k;
+    double inner_tol;
+    int inner_ortho;
 } or_precond;
 
 typedef struct {
     int iters, restarts, converged, mismatch, breakdowns;
     double rel_res_true, rel_res_est;
 } or_info;
+
+static int fgmres_core(int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                       const or_precond *M, const double *b, double *x, int m, double rtol,
+                       int maxiters, int ortho, double *hist, or_info *info, double *dumpV,
+                       double *dumpZ, double *dumpH, int *dump_k, int max_cycles);
 
 static void apply_precond(int64_t n, const or_precond *M, const double *v, double *z)
 {
@@ -575,6 +588,11 @@ static void apply_precond(int64_t n, const or_precond *M, const double *v, doubl
         or_gnp_forward(n, M->rp, M->ci, M->ahat, M->L, M->d, M->h, M->theta, 1, v, z, NULL);
     } else if (M->kind == OR_M_DENSE) {
         for (int64_t i = 0; i < n; ++i) z[i] = dot_seq(n, M->mat + i * n, v);
+    } else if (M->kind == OR_M_GMRES) {
+        or_info inner;
+        memset(z, 0, sizeof(double) * n);
+        fgmres_core(n, M->rp, M->ci, M->aval, NULL, v, z, M->inner_k, M->inner_tol, M->inner_k,
+                    M->inner_ortho, NULL, &inner, NULL, NULL, NULL, NULL, 1);
     } else {
         for (int64_t i = 0; i < n; ++i) z[i] = M->mat[i] * v[i];
     }
@@ -592,7 +610,19 @@ OR_API int or_fgmres(int64_t n, const int32_t *rp, const int32_t *ci, const doub
                      int maxiters, int ortho, double *hist, or_info *info,
                      double *dumpV, double *dumpZ, double *dumpH, int *dump_k)
 {
+    return fgmres_core(n, rp, ci, val, M, b, x, m, rtol, maxiters, ortho, hist, info, dumpV,
+                       dumpZ, dumpH, dump_k, 0);
+}
+
+/* Algorithm 1 as described at or_fgmres; max_cycles > 0 stops after that
+ * many restart cycles (the inner solve of inner-outer GMRES runs one). */
+static int fgmres_core(int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                       const or_precond *M, const double *b, double *x, int m, double rtol,
+                       int maxiters, int ortho, double *hist, or_info *info, double *dumpV,
+                       double *dumpZ, double *dumpH, int *dump_k, int max_cycles)
+{
     memset(info, 0, sizeof(*info));
+    int cycles = 0;
     double *V = (double *)malloc(sizeof(double) * n * (m + 1));
     double *Z = (double *)malloc(sizeof(double) * n * m);
     double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));  /* rotated */
@@ -706,6 +736,7 @@ OR_API int or_fgmres(int64_t n, const int32_t *rp, const int32_t *ci, const doub
         if (!isfinite(beta)) break;
         if (beta <= target) { info->converged = 1; break; }
         if (it >= maxiters) break;
+        if (max_cycles > 0 && ++cycles >= max_cycles) break;
         info->restarts++;
     }
     if (info->rel_res_est > 0.0 && info->rel_res_true > 10.0 * info->rel_res_est) info->mismatch = 1;

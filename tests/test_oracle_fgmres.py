@@ -178,3 +178,90 @@ def test_edge_cases():
     r = O.fgmres(_sys(I.random_small(20, 0.1, 17, diag_shift=6.0)),
                  np.ones(20), 1, 1e-8, 500)
     assert r["info"]["converged"] == 1
+
+
+# --- inner-outer GMRES (Sec. 3, "Compared methods") ---------------------------
+
+def _krylov_argmin(Ad, v, k):
+    """z = argmin over K_k(A, v) of ||v - A z|| (QR of the explicit Krylov basis)."""
+    n = v.size
+    K = np.zeros((n, k))
+    u = v / np.linalg.norm(v)
+    for i in range(k):
+        K[:, i] = u
+        u = Ad @ u
+        u /= np.linalg.norm(u)
+    Q, _ = np.linalg.qr(K)
+    c, *_ = np.linalg.lstsq(Ad @ Q, v, rcond=None)
+    z = Q @ c
+    return z, np.linalg.norm(v - Ad @ z) / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("ortho", [O.MGS, O.CGS2])
+def test_inner_gmres_is_krylov_minimiser(ortho):
+    """Each z_j is the minimum-residual point of K_k(A, v_j), found independently."""
+    A = I.random_small(40, 0.15, 31, diag_shift=3.0)
+    S = _sys(A)
+    Ad = S.A.to_scipy().toarray()
+    b = np.random.default_rng(32).standard_normal(40)
+    k, m = 5, 4
+    r = O.fgmres(S, b, m=m, rtol=1e-14, maxiters=m, M="gmres", inner=(k, 1e-15), ortho=ortho,
+                 dump=True)
+    assert r["k"] == m
+    for j in range(m):
+        v = r["V"][j]
+        zb, _ = _krylov_argmin(Ad, v, k)
+        np.testing.assert_allclose(r["Z"][j], zb, rtol=1e-9, atol=1e-11 * np.abs(zb).max())
+
+
+def test_inner_gmres_one_step_closed_form():
+    """k = 1: the minimiser over span{v} is z = (v^T A v / ||A v||^2) v."""
+    A = I.convdiff3d(4)
+    S = _sys(A)
+    Ad = S.A.to_scipy()
+    b = np.random.default_rng(33).standard_normal(S.n)
+    m = 6
+    r = O.fgmres(S, b, m=m, rtol=1e-14, maxiters=m, M="gmres", inner=(1, 1e-15), dump=True)
+    for j in range(r["k"]):
+        v = r["V"][j]
+        Av = Ad @ v
+        np.testing.assert_allclose(r["Z"][j], (v @ Av) / (Av @ Av) * v, rtol=1e-12, atol=1e-15)
+
+
+def test_inner_gmres_stops_at_its_tolerance():
+    """With tol between the minimal residuals of K_2 and K_3 the inner solve ends after
+    three steps: z_0 is the K_3 minimiser although k = 8."""
+    A = I.random_small(40, 0.15, 34, diag_shift=2.5)
+    S = _sys(A)
+    Ad = S.A.to_scipy().toarray()
+    b = np.random.default_rng(35).standard_normal(40)
+    v = b / np.linalg.norm(b)
+    _, r2 = _krylov_argmin(Ad, v, 2)
+    z3, r3 = _krylov_argmin(Ad, v, 3)
+    assert r3 < 0.95 * r2
+    tol = np.sqrt(r2 * r3)
+    r = O.fgmres(S, b, m=1, rtol=1e-14, maxiters=1, M="gmres", inner=(8, tol), dump=True)
+    np.testing.assert_allclose(r["Z"][0], z3, rtol=1e-9, atol=1e-11 * np.abs(z3).max())
+    assert np.linalg.norm(v - Ad @ r["Z"][0]) <= tol
+
+
+def test_inner_gmres_full_space_is_exact_inverse():
+    """k >= n with a tiny tolerance: z = A^{-1} v, so the outer solve needs one step."""
+    A = I.random_small(20, 0.2, 36, diag_shift=4.0)
+    S = _sys(A)
+    Ad = S.A.to_scipy().toarray()
+    b = np.random.default_rng(37).standard_normal(20)
+    r = O.fgmres(S, b, m=5, rtol=1e-10, maxiters=20, M="gmres", inner=(25, 1e-13))
+    assert r["info"]["iters"] == 1 and r["info"]["converged"] == 1
+    np.testing.assert_allclose(r["x"], np.linalg.solve(Ad, b), rtol=1e-9)
+
+
+def test_inner_gmres_converges_where_restarted_gmres_stalls_less():
+    """Outer FGMRES(10) with inner GMRES(10) needs fewer outer steps than GMRES(10)."""
+    S = _sys(I.convdiff3d(6))
+    b = np.random.default_rng(38).standard_normal(S.n)
+    plain = O.fgmres(S, b, 10, 1e-8, 2000)
+    io = O.fgmres(S, b, 10, 1e-8, 2000, M="gmres", inner=(10, 1e-6))
+    assert plain["info"]["converged"] and io["info"]["converged"]
+    assert io["info"]["iters"] < plain["info"]["iters"]
+    assert io["info"]["rel_res_true"] <= 1e-8
