@@ -406,6 +406,19 @@ def main():
         extra["jacobi_preconditioner"] = {"solves_per_s": rate, "iters": inf5["iters"],
                                           "rel_res_true": inf5["rel_res_true"]}
 
+        # inner-outer GMRES in the paper's setting: outer FGMRES(10), inner
+        # GMRES(10) stopped at relative residual 1e-6
+        def inner_outer():
+            x.zero_()
+            return api.fgmres_solve_gmres(S, b, x=x, m=10, rtol=1e-8, maxiters=args.maxiters,
+                                          inner_k=10, inner_tol=1e-6, prec="f32",
+                                          want_hist=False)[1]
+
+        rate, inf6 = median_rate(inner_outer)
+        extra["inner_outer_gmres"] = {"solves_per_s": rate, "outer_iters": inf6["iters"],
+                                      "rel_res_true": inf6["rel_res_true"],
+                                      "setting": "outer FGMRES(10), inner GMRES(10) to 1e-6, f32"}
+
         # 32 right-hand sides b ~ N(0, I): float32 network one solve at a time,
         # against the bfloat16 network served with 32 concurrent slots
         nb = 32

@@ -200,6 +200,24 @@ GNP_API gnp_status fgmres_solve_jacobi(gnp_system *sys, const double *b_dev, dou
                                        int m, double rtol, int maxiters, gnp_precision prec,
                                        double *hist, gnp_solve_info *info, void *hip_stream);
 
+/* fgmres_solve with inner-outer GMRES: the preconditioner z_j = M(v_j) is
+ * itself an unpreconditioned GMRES solve of A z = v_j, the other comparison
+ * method of Sec. 3 ("Compared methods"; the paper runs inner_k = 10,
+ * inner_tol = 1e-6 with an outer restart of 10).  Each inner solve is one
+ * cycle of at most inner_k Arnoldi steps from z = 0, on the same kernels and
+ * in the same Krylov precision as the outer one (classical Gram-Schmidt
+ * twice, float64 inner products), ended early once its Givens estimate is at
+ * most inner_tol ||v_j||; it takes no true residual.  info.iters counts
+ * outer steps.  The inner workspace (inner_k + 1 basis vectors and a
+ * float64 vector, pitch 32) is kept with the system.
+ * inner_k: 1..31; inner_tol: finite, >= 0 (>= 1 gives z = 0 and a breakdown).
+ * prec: GNP_F32 or GNP_F64.  Errors: as fgmres_solve, plus GNP_EINVAL for
+ * inner_k or inner_tol out of range or another precision. */
+GNP_API gnp_status fgmres_solve_gmres(gnp_system *sys, const double *b_dev, double *x_dev,
+                                      int m, double rtol, int maxiters, int inner_k,
+                                      double inner_tol, gnp_precision prec, double *hist,
+                                      gnp_solve_info *info, void *hip_stream);
+
 
 /* Solve A x_k = b_k for nrhs right-hand sides at once (each one exactly as
  * fgmres_solve would, step for step), with one network application per

@@ -252,6 +252,30 @@ def fgmres_solve_jacobi(system: System, b: torch.Tensor, x: torch.Tensor | None 
     return x, d, hist
 
 
+def fgmres_solve_gmres(system: System, b: torch.Tensor, x: torch.Tensor | None = None,
+                       m: int = 10, rtol: float = 1e-8, maxiters: int = 100, inner_k: int = 10,
+                       inner_tol: float = 1e-6, prec="f32", want_hist: bool = True,
+                       stream=None):
+    """Algorithm 1 with inner-outer GMRES as M (fgmres_solve_gmres): z_j = one
+    cycle of at most inner_k GMRES steps on A z = v_j, ended at inner_tol.
+    Returns (x, info dict, hist ndarray or None)."""
+    p = PREC[prec]
+    if x is None:
+        x = torch.zeros(system.n, dtype=torch.float64, device=b.device)
+    hist = np.full(maxiters + 1, np.nan) if want_hist else None
+    info = SolveInfo()
+    check(_lib.load().fgmres_solve_gmres(
+        system.handle, _dev_ptr(b, torch.float64, system.n, "b"),
+        _dev_ptr(x, torch.float64, system.n, "x"), int(m), float(rtol), int(maxiters),
+        int(inner_k), float(inner_tol), p,
+        hist.ctypes.data_as(C.c_void_p) if hist is not None else None, C.byref(info),
+        _stream(stream)))
+    d = info.as_dict()
+    if hist is not None:
+        hist = hist[: d["iters"] + 1]
+    return x, d, hist
+
+
 def fgmres_solve_batch(system: System, B: torch.Tensor, model: Model, X: torch.Tensor | None = None,
                        m: int = 30, rtol: float = 1e-8, maxiters: int = 100, prec="bf16",
                        stream=None):

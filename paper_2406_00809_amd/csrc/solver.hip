@@ -215,6 +215,76 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(int64_t n, const double *__res
 }
 
 // ---------------------------------------------------------------------------
+// Inner-outer GMRES (the comparison method of Sec. 3, "Compared methods"):
+// z_j is the result of one cycle of at most k unpreconditioned Arnoldi steps
+// on A z = v_j from z = 0, ended once the Givens estimate is <= tol ||v_j||.
+// The inner cycle runs on the step kernels below with a context of its own;
+// k_inner_begin/k_inner_start set it up from v_j (r = v_j, x = 0, beta =
+// ||v_j||), k_inner_end hands its float64 solution back as z_j.  Once the
+// outer cycle is over they do nothing, and k_inner_start marks the inner
+// cycle over too, so that every kernel of the inner cycle exits at entry.
+// ---------------------------------------------------------------------------
+template <typename KT>
+__global__ __launch_bounds__(BLOCK) void k_inner_begin(int64_t n, const KT *__restrict__ v,
+                                                       double *__restrict__ r,
+                                                       double *__restrict__ x,
+                                                       double *__restrict__ partial,
+                                                       const Ctl *outer) {
+    __shared__ double sh[BLOCK / WAVE];
+    if (outer->cycle_done) return;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BLOCK) {
+        const double vi = (double)v[i];
+        r[i] = vi;
+        x[i] = 0.0;
+        s += vi * vi;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_inner_start(int nblk, const double *partial,
+                                                       double tol, int k, Ctl *ctl, double *g,
+                                                       const Ctl *outer) {
+    __shared__ double res[1];
+    if (outer->cycle_done) {
+        if (threadIdx.x == 0) {
+            ctl->cycle_done = 1;
+            ctl->kcols = 0;
+            ctl->kuse = 0;
+        }
+        return;
+    }
+    reduce_columns(nblk, 1, partial, 1, res);
+    const double beta = sqrt(res[0]);
+    if (threadIdx.x == 0) {
+        Ctl c;
+        memset(&c, 0, sizeof(c));
+        c.m = k;
+        c.maxiters = k;
+        c.bnorm = beta;
+        c.beta = beta;
+        c.target = tol * beta;
+        c.est = beta;
+        c.est_rel = 1.0;
+        c.rel_true = 1.0;
+        c.cycle_done = beta > c.target ? 0 : 1;  // v = 0 or tol >= 1: z = 0
+        *ctl = c;
+    }
+    for (int i = threadIdx.x; i <= k; i += BLOCK) g[i] = (i == 0) ? beta : 0.0;
+}
+
+template <typename KT>
+__global__ __launch_bounds__(BLOCK) void k_inner_end(int64_t n, const double *__restrict__ x,
+                                                     KT *__restrict__ z, const Ctl *outer) {
+    if (outer->cycle_done) return;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BLOCK)
+        z[i] = (KT)x[i];
+}
+
+// ---------------------------------------------------------------------------
 // v = src / div into vcur (contiguous), div = beta (cycle start) or
 // h_{j+1,j}.  The basis column of v is written by the next step's first
 // Gram-Schmidt pass, which reads that row of the basis anyway.  (With a
@@ -617,6 +687,11 @@ static int64_t cgs_rpb(int64_t n) {
 
 void solve_ctx_free(SolveCtx *c) {
     if (!c) return;
+    if (c->inner) {
+        solve_ctx_free(c->inner);
+        delete c->inner;
+    }
+    if (c->inner_x) (void)hipFree(c->inner_x);
     void *ptrs[] = {c->V,  c->Z,  c->w,  c->r,  c->act[0], c->act[1], c->tau, c->H,
                     c->H0, c->cs, c->sn, c->g,  c->y,      c->h1,     c->h2,  c->hist,
                     c->partial, c->counters, c->ctl, c->vcur};
@@ -707,7 +782,8 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     const bool corr_in_encoder = v_in_encoder && MP == 32;
     // Jacobi: z_j = D^{-1} v_j; with any preconditioner z_j is kept in Z
     const bool jac = !model && c->precond == PRECOND_JACOBI;
-    const bool flex = model || jac;
+    const bool inner = !model && c->precond == PRECOND_GMRES;
+    const bool flex = model || jac || inner;
     hipLaunchKernelGGL((k_normalize<KT, double>), dim3(sg), dim3(BLOCK), 0, st, n, c->r, vcur,
                        c->ctl, 1, Bat{});
     if (model)
@@ -733,6 +809,20 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
             hipLaunchKernelGGL((k_jacobi<KT>), dim3(sg), dim3(BLOCK), 0, st, n,
                                (const double *)s->dinv64, (const KT *)vcur, zj,
                                (const Ctl *)c->ctl);
+        else if (inner) {
+            // float64 bases accumulate the inner solution in z_j itself
+            SolveCtx *ic = c->inner;
+            double *xin = sizeof(KT) == 8 ? (double *)zj : c->inner_x;
+            hipLaunchKernelGGL((k_inner_begin<KT>), dim3(sg), dim3(BLOCK), 0, st, n,
+                               (const KT *)vcur, ic->r, xin, ic->partial, (const Ctl *)c->ctl);
+            hipLaunchKernelGGL(k_inner_start, dim3(1), dim3(BLOCK), 0, st, sg,
+                               (const double *)ic->partial, c->inner_tol, c->inner_k, ic->ctl,
+                               ic->g, (const Ctl *)c->ctl);
+            GNP_TRY((launch_cycle_mp<KT, 32>(ic, nullptr, c->inner_k, xin, st)));
+            if (sizeof(KT) != 8)
+                hipLaunchKernelGGL((k_inner_end<KT>), dim3(sg), dim3(BLOCK), 0, st, n,
+                                   (const double *)xin, zj, (const Ctl *)c->ctl);
+        }
         spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st, 1, 1, 0, 0,
                                 s->max_row);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
@@ -1171,6 +1261,37 @@ extern "C" gnp_status fgmres_solve_jacobi(gnp_system *sys, const double *b_dev, 
     GNP_TRY(solve_ctx_prepare(c, sys, m, maxiters, prec, 0));
     c->prec = prec;
     c->precond = PRECOND_JACOBI;
+    const gnp_status r = solve_run(c, nullptr, b_dev, x_dev, m, rtol, maxiters, hist, info, st);
+    c->precond = PRECOND_MODEL;
+    return r;
+}
+
+extern "C" gnp_status fgmres_solve_gmres(gnp_system *sys, const double *b_dev, double *x_dev,
+                                         int m, double rtol, int maxiters, int inner_k,
+                                         double inner_tol, gnp_precision prec, double *hist,
+                                         gnp_solve_info *info, void *hip_stream) {
+    if (!sys || !b_dev || !x_dev) return fail(GNP_EINVAL, "null argument");
+    if (m < 1 || m > 255) return fail(GNP_EINVAL, "m must be in [1, 255]");
+    if (!(rtol > 0.0)) return fail(GNP_EINVAL, "rtol must be > 0");
+    if (maxiters < 1) return fail(GNP_EINVAL, "maxiters must be >= 1");
+    if (inner_k < 1 || inner_k > 31) return fail(GNP_EINVAL, "inner_k must be in [1, 31]");
+    if (!(inner_tol >= 0.0) || !std::isfinite(inner_tol))
+        return fail(GNP_EINVAL, "inner_tol must be finite and >= 0");
+    if (prec != GNP_F32 && prec != GNP_F64)
+        return fail(GNP_EINVAL, "inner-outer GMRES runs in float32 or float64");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!sys->solve_cache) sys->solve_cache = new SolveCtx();
+    SolveCtx *c = (SolveCtx *)sys->solve_cache;
+    GNP_TRY(solve_ctx_prepare(c, sys, m, maxiters, prec, 0));
+    c->prec = prec;
+    if (!c->inner) c->inner = new SolveCtx();
+    GNP_TRY(solve_ctx_prepare(c->inner, sys, inner_k, inner_k, prec, 0));
+    c->inner->prec = prec;
+    c->inner->precond = PRECOND_MODEL;
+    if (!c->inner_x) GNP_HIP(hipMalloc(&c->inner_x, sizeof(double) * sys->n));
+    c->inner_k = inner_k;
+    c->inner_tol = inner_tol;
+    c->precond = PRECOND_GMRES;
     const gnp_status r = solve_run(c, nullptr, b_dev, x_dev, m, rtol, maxiters, hist, info, st);
     c->precond = PRECOND_MODEL;
     return r;

@@ -36,11 +36,12 @@ struct Bat {
 };
 
 // Preconditioner of a solve besides the network (which is passed as a model)
-enum PrecondKind { PRECOND_MODEL = 0, PRECOND_JACOBI = 1 };
+enum PrecondKind { PRECOND_MODEL = 0, PRECOND_JACOBI = 1, PRECOND_GMRES = 2 };
 
 struct SolveCtx {
     gnp_system *sys = nullptr;
-    int precond = PRECOND_MODEL;  // PRECOND_JACOBI: z_j = D^{-1} v_j (sys->dinv64)
+    int precond = PRECOND_MODEL;  // PRECOND_JACOBI: z_j = D^{-1} v_j (sys->dinv64);
+                                  // PRECOND_GMRES: z_j = inner GMRES on A z = v_j
     int m = 0;
     int mp = 32;            // row pitch of the interleaved basis
     int maxiters_cap = 0;
@@ -66,6 +67,12 @@ struct SolveCtx {
     Ctl *ctl = nullptr;
     Ctl *ctl_host = nullptr;  // pinned
     hipEvent_t ev = nullptr;
+    // inner-outer GMRES: the inner solve's own context (m = inner_k, no
+    // preconditioner) and its float64 solution
+    SolveCtx *inner = nullptr;
+    double *inner_x = nullptr;
+    int inner_k = 0;
+    double inner_tol = 0.0;
 };
 
 gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
