@@ -338,3 +338,20 @@ def fgmres(S: System, b, m, rtol, maxiters, M="identity", theta=None, arch=None,
     if dump:
         out.update(V=V, Z=Z, H=H, k=k.value)
     return out
+
+
+# --- evaluation metrics (Sec. 3, "Evaluation metrics") ------------------------
+
+_TINY = np.finfo(np.float64).tiny  # a zero residual counts as the smallest normal double
+
+
+def iter_auc(r, rtol):
+    """Area under the log10 relative-residual curve over iterations i = 0..iters,
+    measured from log10(rtol)."""
+    return float(sum(np.log10(max(float(ri), _TINY)) - np.log10(rtol) for ri in r))
+
+
+def time_auc(r, t, rtol):
+    """Right-endpoint sum over i = 1..iters of (log10 r_i - log10 rtol)(t_i - t_{i-1})."""
+    return float(sum((np.log10(max(float(r[i]), _TINY)) - np.log10(rtol)) * (t[i] - t[i - 1])
+                     for i in range(1, len(r))))
