@@ -219,6 +219,27 @@ GNP_API gnp_status fgmres_solve_gmres(gnp_system *sys, const double *b_dev, doub
                                       gnp_solve_info *info, void *hip_stream);
 
 
+/* Elapsed wall-clock time of the last single solve on this system
+ * (fgmres_solve, fgmres_solve_jacobi or fgmres_solve_gmres), for the
+ * Time-AUC metric of Sec. 3 ("Evaluation metrics"): t_host[i] = seconds from
+ * the moment the initial residual r_0 was known to the moment the residual
+ * estimate of Arnoldi step i was known (t_host[0] = 0), stamped on the device
+ * with its wall clock, so host waits between restart cycles are included.
+ * t_host: host array of count doubles, count in [1, iters + 1] of that solve.
+ * Errors: GNP_EINVAL for no solve yet or count out of range. */
+GNP_API gnp_status fgmres_step_times(gnp_system *sys, double *t_host, int count);
+
+/* The two metrics of Sec. 3 ("Evaluation metrics") from a residual history
+ * (host arrays): Iter-AUC = sum over i = 0..iters of log10 r_i - log10 rtol,
+ * Time-AUC = sum over i = 1..iters of (log10 r_i - log10 rtol)(t_i - t_{i-1}).
+ * r: iters + 1 relative residuals (the hist of a solve: r_0 true, then the
+ * Givens estimates); t: iters + 1 times (fgmres_step_times), needed only for
+ * time_auc.  A residual of 0 counts as the smallest normal double.  Either
+ * output may be NULL.  Errors: GNP_EINVAL for r = NULL, iters < 0, rtol <= 0,
+ * or time_auc without t.  Host-only: no device work. */
+GNP_API gnp_status gnp_auc(const double *r, const double *t, int iters, double rtol,
+                           double *iter_auc, double *time_auc);
+
 /* Solve A x_k = b_k for nrhs right-hand sides at once (each one exactly as
  * fgmres_solve would, step for step), with one network application per
  * Arnoldi step for the whole batch (Sec. 2.2: one preconditioner serves every

@@ -276,6 +276,28 @@ def fgmres_solve_gmres(system: System, b: torch.Tensor, x: torch.Tensor | None =
     return x, d, hist
 
 
+def fgmres_step_times(system: System, count: int) -> np.ndarray:
+    """Seconds from r_0 to each Arnoldi step's residual estimate of the last
+    single solve on `system` (fgmres_step_times); count = iters + 1."""
+    t = np.zeros(int(count))
+    check(_lib.load().fgmres_step_times(system.handle, t.ctypes.data_as(C.c_void_p), int(count)))
+    return t
+
+
+def auc(hist, rtol: float, t=None):
+    """(Iter-AUC, Time-AUC or None) of a residual history (gnp_auc, Sec. 3)."""
+    r = np.ascontiguousarray(hist, dtype=np.float64)
+    tt = None if t is None else np.ascontiguousarray(t, dtype=np.float64)
+    if tt is not None and tt.size != r.size:
+        raise ValueError("t must have one entry per residual")
+    ia, ta = C.c_double(), C.c_double()
+    check(_lib.load().gnp_auc(r.ctypes.data_as(C.c_void_p),
+                              None if tt is None else tt.ctypes.data_as(C.c_void_p),
+                              r.size - 1, float(rtol), C.byref(ia),
+                              None if tt is None else C.byref(ta)))
+    return ia.value, (None if tt is None else ta.value)
+
+
 def fgmres_solve_batch(system: System, B: torch.Tensor, model: Model, X: torch.Tensor | None = None,
                        m: int = 30, rtol: float = 1e-8, maxiters: int = 100, prec="bf16",
                        stream=None):

@@ -22,6 +22,7 @@
 // one round).
 // The host synchronises once per restart cycle; every kernel of a step exits
 // at entry once the device-side control block says the cycle is over.
+#include <float.h>
 #include <math.h>
 #include <string.h>
 
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual(int64_t n, const int32_t *__
 // beta = ||r||; convergence / iteration-limit decision; restart bookkeeping
 __global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *partial, Ctl *ctl,
                                                         double *g, double *hist, int initial,
-                                                        Bat bt) {
+                                                        Bat bt, uint64_t *tstamp) {
     __shared__ double res[1];
     partial += blockIdx.y * bt.part;
     ctl += blockIdx.y;
@@ -166,6 +167,7 @@ __global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *
         ctl->beta = beta;
         if (initial) {
             if (hist) hist[0] = rel;
+            if (tstamp) tstamp[0] = (uint64_t)wall_clock64();
             ctl->est_rel = rel;
         }
         if (!isfinite(beta)) {
@@ -499,7 +501,7 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const dou
                                                       int pstride, const double *h1, double *h2,
                                                       Ctl *ctl, double *H, double *H0,
                                                       double *cs, double *sn, double *g,
-                                                      double *hist, Bat bt) {
+                                                      double *hist, Bat bt, uint64_t *tstamp) {
     {
         const int bi = blockIdx.y;
         ctl += bi;
@@ -563,6 +565,7 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const dou
         ctl->it += 1;
         ctl->kcols = j + 1;
         if (hist) hist[ctl->it] = est / ctl->bnorm;
+        if (tstamp) tstamp[ctl->it] = (uint64_t)wall_clock64();
         if (!isfinite(hn) || !isfinite(rho) || !isfinite(est)) {
             ctl->nonfinite = 1;
             ctl->solve_done = 1;
@@ -694,7 +697,7 @@ void solve_ctx_free(SolveCtx *c) {
     if (c->inner_x) (void)hipFree(c->inner_x);
     void *ptrs[] = {c->V,  c->Z,  c->w,  c->r,  c->act[0], c->act[1], c->tau, c->H,
                     c->H0, c->cs, c->sn, c->g,  c->y,      c->h1,     c->h2,  c->hist,
-                    c->partial, c->counters, c->ctl, c->vcur};
+                    c->partial, c->counters, c->ctl, c->vcur, c->tstamp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->ctl_host) (void)hipHostFree(c->ctl_host);
@@ -710,7 +713,7 @@ size_t solve_ctx_bytes(int64_t n, int m, int maxiters, gnp_precision prec, int a
     const int64_t npartial = std::max<int64_t>(nb_cgs * (mp + 1), 2048);
     size_t b = kb * (size_t)n * (mp + m + 2) + sizeof(double) * n;
     if (act_d > 0) b += 2 * kb * (size_t)n * act_d;
-    b += sizeof(double) * (4 + 2 * (m + 1) * m + 3 * m + 3 * (m + 1) + cap + 1 + npartial);
+    b += sizeof(double) * (4 + 2 * (m + 1) * m + 3 * m + 3 * (m + 1) + 2 * (cap + 1) + npartial);
     b += sizeof(Ctl);
     return b;
 }
@@ -750,6 +753,7 @@ gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,
     GNP_HIP(hipMalloc(&c->h1, sizeof(double) * (m + 1)));
     GNP_HIP(hipMalloc(&c->h2, sizeof(double) * (m + 1)));
     GNP_HIP(hipMalloc(&c->hist, sizeof(double) * (c->maxiters_cap + 1)));
+    GNP_HIP(hipMalloc(&c->tstamp, sizeof(uint64_t) * (c->maxiters_cap + 1)));
     const int64_t nb_cgs = (n + cgs_rpb(n) - 1) / cgs_rpb(n);
     c->npartial = std::max<int64_t>(nb_cgs * (c->mp + 1), 2048);
     GNP_HIP(hipMalloc(&c->partial, sizeof(double) * c->npartial));
@@ -835,7 +839,7 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                            Bat{}, (const KT *)nullptr);
         hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
-                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, Bat{});
+                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, Bat{}, c->tstamp);
         if (!corr_in_encoder)
             hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j,
                                w, (const double *)c->h2, c->partial, pstride,
@@ -888,7 +892,8 @@ static void launch_residual(SolveCtx *c, const double *b, const double *x, int i
         hipLaunchKernelGGL(k_residual<16>, dim3(grid), dim3(BLOCK), 0, st, n, s->rp, s->ci,
                            s->val64, x, b, c->r, c->partial, Bat{});
     hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(BLOCK), 0, st, grid,
-                       (const double *)c->partial, c->ctl, c->g, c->hist, initial, Bat{});
+                       (const double *)c->partial, c->ctl, c->g, c->hist, initial, Bat{},
+                       c->tstamp);
 }
 
 gnp_status solve_begin(SolveCtx *c, const double *b, const double *x, int m, double rtol,
@@ -1076,7 +1081,8 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
                            bt, (const float *)nullptr);
         hipLaunchKernelGGL(k_fin_givens, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
-                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, bt);
+                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, bt,
+                           (uint64_t *)nullptr);
         hipLaunchKernelGGL((k_cgs<float, MP, 2>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)c->h2, c->partial, pstride, (const Ctl *)c->ctl,
                            bt, (const float *)nullptr);
@@ -1112,7 +1118,8 @@ static void batch_residual(BatchCtx *c, const double *b, const double *x, int in
         hipLaunchKernelGGL(k_residual<16>, gg, dim3(BLOCK), 0, st, n, s->rp, s->ci, s->val64, x,
                            b, c->r, c->partial, c->bt);
     hipLaunchKernelGGL(k_fin_residual, dim3(1, c->nb), dim3(BLOCK), 0, st, grid,
-                       (const double *)c->partial, c->ctl, c->g, c->hist, initial, c->bt);
+                       (const double *)c->partial, c->ctl, c->g, c->hist, initial, c->bt,
+                       (uint64_t *)nullptr);
 }
 
 static gnp_status batch_run(BatchCtx *c, gnp_model *model, const double *b, double *x, int m,
@@ -1295,6 +1302,42 @@ extern "C" gnp_status fgmres_solve_gmres(gnp_system *sys, const double *b_dev, d
     const gnp_status r = solve_run(c, nullptr, b_dev, x_dev, m, rtol, maxiters, hist, info, st);
     c->precond = PRECOND_MODEL;
     return r;
+}
+
+extern "C" gnp_status fgmres_step_times(gnp_system *sys, double *t_host, int count) {
+    if (!sys || !t_host) return fail(GNP_EINVAL, "null argument");
+    SolveCtx *c = (SolveCtx *)sys->solve_cache;
+    if (!c || !c->tstamp || !c->ctl_host) return fail(GNP_EINVAL, "no solve on this system yet");
+    if (count < 1 || count > c->ctl_host->it + 1)
+        return fail(GNP_EINVAL, "count must be in [1, iters + 1] of the last solve");
+    int dev = 0, khz = 0;
+    GNP_HIP(hipGetDevice(&dev));
+    GNP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(GNP_EDEVICE, "device reports no wall-clock rate");
+    std::vector<uint64_t> ts(count);
+    GNP_HIP(hipMemcpy(ts.data(), c->tstamp, sizeof(uint64_t) * count, hipMemcpyDeviceToHost));
+    for (int i = 0; i < count; ++i)
+        t_host[i] = (double)(int64_t)(ts[i] - ts[0]) / (1e3 * (double)khz);
+    return GNP_OK;
+}
+
+extern "C" gnp_status gnp_auc(const double *r, const double *t, int iters, double rtol,
+                              double *iter_auc, double *time_auc) {
+    if (!r || iters < 0 || !(rtol > 0.0) || (time_auc && !t))
+        return fail(GNP_EINVAL, "bad argument");
+    // a zero residual (b = 0, an exact step) is taken at the smallest normal double
+    auto lg = [&](double v) { return log10(v > DBL_MIN ? v : DBL_MIN) - log10(rtol); };
+    if (iter_auc) {
+        double a = 0.0;
+        for (int i = 0; i <= iters; ++i) a += lg(r[i]);
+        *iter_auc = a;
+    }
+    if (time_auc) {
+        double a = 0.0;
+        for (int i = 1; i <= iters; ++i) a += lg(r[i]) * (t[i] - t[i - 1]);
+        *time_auc = a;
+    }
+    return GNP_OK;
 }
 
 extern "C" gnp_status fgmres_solve_batch(gnp_system *sys, gnp_model *model, const double *b_dev,

@@ -61,6 +61,9 @@ struct SolveCtx {
     double *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
     double *h1 = nullptr, *h2 = nullptr;  // CGS2 pass coefficients
     double *hist = nullptr;               // maxiters_cap + 1
+    // wall-clock stamps (wall_clock64 ticks): [0] once r_0 is known, [i] once
+    // step i's residual estimate is known; maxiters_cap + 1
+    uint64_t *tstamp = nullptr;
     double *partial = nullptr;
     int64_t npartial = 0;
     unsigned *counters = nullptr;

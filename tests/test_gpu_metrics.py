@@ -1,0 +1,76 @@
+"""Iter-AUC / Time-AUC (Sec. 3, "Evaluation metrics") through the C ABI:
+the device-stamped step times of a solve and the library's metrics against
+the oracle's definitions on the same history; the GPU solve's Iter-AUC
+against the oracle solve's."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_00809_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    from paper_2406_00809_amd import api as A
+    return A
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("m", [10, 30])
+def test_step_times_and_auc_match_oracle(api, m):
+    import torch
+    A = I.laplace2d(24)
+    S = api.System(A)
+    ref = O.System(A)
+    b = I.rhs_normal(A.n, 21)
+    bd = _dev(b)
+    api.fgmres_solve(S, bd, None, m=m, rtol=1e-8, maxiters=600, prec="f64")  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info, hist = api.fgmres_solve(S, bd, None, m=m, rtol=1e-8, maxiters=600, prec="f64")
+    wall = time.perf_counter() - t0
+    it = info["iters"]
+    assert info["converged"] == 1 and (m == 30 or info["restarts"] >= 1)
+    t = api.fgmres_step_times(S, it + 1)
+    assert t[0] == 0.0 and np.all(np.diff(t) >= 0.0) and t[-1] > 0.0
+    assert t[-1] <= wall
+    ia, ta = api.auc(hist, 1e-8, t)
+    assert ia == pytest.approx(O.iter_auc(hist, 1e-8), rel=1e-12, abs=1e-12)
+    assert ta == pytest.approx(O.time_auc(hist, t, 1e-8), rel=1e-12, abs=1e-15)
+    r = O.fgmres(ref, b, m, 1e-8, 600, ortho=O.CGS2)
+    assert abs(r["info"]["iters"] - it) <= 1
+    k = min(it, r["info"]["iters"]) + 1
+    assert O.iter_auc(hist[:k], 1e-8) == pytest.approx(O.iter_auc(r["hist"][:k], 1e-8), abs=1e-5)
+    ia2, ta2 = api.auc(hist, 1e-8)
+    assert ia2 == ia and ta2 is None
+
+
+def test_step_times_follow_every_single_solve_kind(api):
+    A = I.convdiff3d(10)
+    S = api.System(A)
+    bd = _dev(I.rhs_normal(A.n, 22))
+    from paper_2406_00809_amd._lib import GNPError
+    for run in (lambda: api.fgmres_solve_jacobi(S, bd, m=20, maxiters=200, prec="f32"),
+                lambda: api.fgmres_solve_gmres(S, bd, m=10, maxiters=100, prec="f32")):
+        _, info, hist = run()
+        t = api.fgmres_step_times(S, info["iters"] + 1)
+        assert t[0] == 0.0 and np.all(np.diff(t) >= 0.0)
+        ia, ta = api.auc(hist, 1e-8, t)
+        assert ia == pytest.approx(O.iter_auc(hist, 1e-8), rel=1e-12)
+        assert ta == pytest.approx(O.time_auc(hist, t, 1e-8), rel=1e-12, abs=1e-15)
+        with pytest.raises(GNPError):
+            api.fgmres_step_times(S, info["iters"] + 2)
+    with pytest.raises(GNPError):
+        api.fgmres_step_times(api.System(I.laplace2d(4)), 1)
+    with pytest.raises(GNPError):
+        api.auc([1.0, 0.1], 0.0)
