@@ -6,6 +6,7 @@ it.  See oracle.c for the readings of the paper that it implements.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -49,6 +50,8 @@ def lib():
             build()
         L = C.CDLL(LIB)
         L.or_num_threads.restype = C.c_int
+        L.or_set_scaling.argtypes = [C.c_int]
+        L.or_set_scaling.restype = None
         L.or_set_num_threads.argtypes = [C.c_int]
         L.or_set_num_threads.restype = None
         L.or_spmm.argtypes = [C.c_int64, I32P, I32P, F64P, C.c_int, F64P, F64P]
@@ -94,6 +97,17 @@ def _c64(a):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+@contextlib.contextmanager
+def without_scaling():
+    """Within the block every oracle call uses the network without the scaling
+    of Eq. (6) (s = s^-1 = identity: the ablation of Sec. 3)."""
+    lib().or_set_scaling(0)
+    try:
+        yield
+    finally:
+        lib().or_set_scaling(1)
 
 
 def set_num_threads(k: int) -> None:

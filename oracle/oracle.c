@@ -213,6 +213,12 @@ static void fwd_free(fwd_state *s, int L)
 
 static double relu(double x) { return x > 0.0 ? x : 0.0; }
 
+/* 0: the network without the scaling of Eq. (6), s = s^-1 = identity (the
+ * ablation of Sec. 3 that asks whether scale equivariance is needed); it
+ * applies to every forward pass, loss, gradient, training run and solve. */
+static int g_scaled = 1;
+OR_API void or_set_scaling(int on) { g_scaled = on ? 1 : 0; }
+
 /* Forward pass: Eq. (6) scaling, MLP encoder, L Res-GCONV layers (Eq. (5))
  * with A-hat from Eq. (4), MLP decoder, back-scaling. */
 static void gnp_forward_state(int64_t n, const int32_t *rp, const int32_t *ci, const double *ahat,
@@ -228,8 +234,8 @@ static void gnp_forward_state(int64_t n, const int32_t *rp, const int32_t *ci, c
         for (int64_t i = 0; i < n; ++i) ss += bin[i * B + b] * bin[i * B + b];
         double tau = sqrt(ss);
         s->tau[b] = tau;
-        s->si[b] = tau > 0.0 ? sqn / tau : 0.0;
-        s->so[b] = tau / sqn;
+        s->si[b] = g_scaled ? (tau > 0.0 ? sqn / tau : 0.0) : 1.0;
+        s->so[b] = g_scaled ? tau / sqn : 1.0;
     }
     const int64_t rows = n * B;
     /* encoder: E = ReLU(u W1 + c1) W2 + c2 */

@@ -241,6 +241,16 @@ def test_gradient_central_differences():
     """Central differences (h = 1e-6, FP64) along random directions.  A
     direction is used only when the step-h and step-h/2 quotients agree to
     1e-7 (no ReLU or |.| kink crossed inside the stencil)."""
+    _check_central_differences()
+
+
+def test_gradient_central_differences_without_scaling():
+    """The same check for the network without the scaling of Eq. (6)."""
+    with O.without_scaling():
+        _check_central_differences()
+
+
+def _check_central_differences():
     S = _sys(I.laplace2d(8))
     L, d, h, B = 2, 4, 8, 3
     th = _rand_model(S, L, d, h, 41)
@@ -279,3 +289,38 @@ def test_multi_rhs_columns_independent():
     Z = O.gnp_forward(S, 2, 5, 7, th, bb)
     for c in range(3):
         np.testing.assert_array_equal(Z[:, c], O.gnp_forward(S, 2, 5, 7, th, bb[:, c].copy()))
+
+
+# --- without the scaling of Eq. (6) (the ablation of Sec. 3) -----------------
+
+def test_without_scaling_equals_scaled_at_norm_sqrt_n():
+    """For ||b|| = sqrt(n) the factors sqrt(n)/tau and tau/sqrt(n) are exactly
+    1, so the network without them gives the same bits; at other norms it is
+    no longer scale-equivariant, and the switch is back on after the block."""
+    S = _sys(I.convdiff3d(6))
+    L, d, h = 3, 8, 16
+    th = _rand_model(S, L, d, h, 5)
+    b = np.where(np.random.default_rng(6).standard_normal(S.n) > 0, 1.0, -1.0)
+    z1 = O.gnp_forward(S, L, d, h, th, b)
+    with O.without_scaling():
+        z2 = O.gnp_forward(S, L, d, h, th, b)
+        z3 = O.gnp_forward(S, L, d, h, th, 4.0 * b)
+    np.testing.assert_array_equal(z1, z2)
+    assert np.linalg.norm(z3 - 4.0 * z1) > 1e-3 * np.linalg.norm(z1)
+    np.testing.assert_array_equal(O.gnp_forward(S, L, d, h, th, 4.0 * b), 4.0 * z1)
+
+
+def test_without_scaling_zero_input_closed_form():
+    """L = 0 without Eq. (6): M(0) = ReLU((ReLU(c1) W2 + c2) W3 + c3) W4 + c4 in
+    every row (with the scaling M(0) = 0)."""
+    S = _sys(I.laplace2d(5))
+    d, h = 4, 8
+    th = _rand_model(S, 0, d, h, 7)
+    lay = I.param_layout(0, d, h)
+    P = {k: th[o:o + n] for k, (o, n) in lay.items()}
+    E = np.maximum(P["c1"], 0) @ P["W2"].reshape(h, d) + P["c2"]
+    o = np.maximum(E @ P["W3"].reshape(d, h) + P["c3"], 0) @ P["W4"] + P["c4"][0]
+    with O.without_scaling():
+        z = O.gnp_forward(S, 0, d, h, th, np.zeros(S.n))
+    np.testing.assert_allclose(z, np.full(S.n, o), rtol=1e-13)
+    assert np.all(O.gnp_forward(S, 0, d, h, th, np.zeros(S.n)) == 0.0)
