@@ -281,6 +281,9 @@ def main():
     ap.add_argument("--sampler-compare", action="store_true",
                     help="also train a network with the Arnoldi sampler of Eq. (3) (m = 40, "
                          "half of every batch) and report its iterations and solves/s")
+    ap.add_argument("--scale-ablation", action="store_true",
+                    help="also train a network without the scaling of Eq. (6) (same initial "
+                         "weights, steps and seed) and report its loss, iterations and solves/s")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the float32-network comparison solves")
     args = ap.parse_args()
@@ -534,6 +537,37 @@ def main():
                                     "rel_res_true": inf2["rel_res_true"], "train_s": tr2,
                                     "train_loss_first_best": [float(h2[0]), float(h2[b2])]}
         log(f"sampler-trained network: {inf2['iters']} its, {extra['sampler_trained']}")
+
+    if args.scale_ablation:
+        # the ablation of Sec. 3: the same network and training run without
+        # s, s^-1 of Eq. (6); the solver hands it unit-norm basis vectors as
+        # they are
+        M3 = api.Model(S, L, d, h, th0)
+        M3.set_scaling(False)
+        t1 = time.perf_counter()
+        h3, b3 = M3.train(args.train_steps, 32, lr=1e-3, seed=2, prec="f32")
+        torch.cuda.synchronize()
+        tr3 = time.perf_counter() - t1
+        abl = {"train_s": tr3, "train_loss_first_best": [float(h3[0]), float(h3[b3])]}
+        for mm in (m, 40):
+            x3 = torch.zeros(S.n, dtype=torch.float64, device=dev)
+            api.fgmres_solve(S, b, M3, x=x3, m=mm, rtol=1e-8, maxiters=args.maxiters,
+                             prec=args.prec, want_hist=False)
+            x3.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, inf3, hh3 = api.fgmres_solve(S, b, M3, x=x3, m=mm, rtol=1e-8,
+                                            maxiters=args.maxiters, prec=args.prec)
+            torch.cuda.synchronize()
+            abl[f"m{mm}"] = {"solves_per_s": 1.0 / (time.perf_counter() - t1),
+                             "iters": inf3["iters"], "converged": inf3["converged"],
+                             "rel_res_true": inf3["rel_res_true"],
+                             "iter_auc": api.auc(hh3, 1e-8)[0]}
+        _, inf1, hh1 = api.fgmres_solve(S, b, M, m=m, rtol=1e-8, maxiters=args.maxiters,
+                                        prec=args.prec)
+        abl["with_scaling_iter_auc"] = api.auc(hh1, 1e-8)[0]
+        extra["without_eq6_scaling"] = abl
+        log(f"network without Eq. (6) scaling: {abl}")
 
     # ---- dominant kernel: one Res-GCONV layer, same launch configuration
     lay_ms = M.time_layer(nrhs=1, prec=args.prec, reps=200)

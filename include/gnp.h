@@ -126,6 +126,14 @@ GNP_API gnp_status gnp_model_create(gnp_system *sys, int L, int d, int h,
                                     const double *init_params, gnp_model **out);
 GNP_API void gnp_model_destroy(gnp_model *model);
 GNP_API size_t gnp_model_nparams(const gnp_model *model);
+/* Switch the scale-equivariant wrapping of Eq. (6) off (on = 0) or back on
+ * (on = 1, the default) for every later apply, training step and solve: off,
+ * the network is applied to b itself, z = decoder(layers(encoder(b))), the
+ * alternative the paper's ablation compares against (Sec. 3, whether the
+ * scale-equivariance design is necessary).  Off, M(0) is the network's
+ * output for a zero input instead of 0.  Errors: GNP_EINVAL for a null model
+ * or another value of on. */
+GNP_API gnp_status gnp_model_set_scaling(gnp_model *model, int on);
 GNP_API gnp_status gnp_params_get(const gnp_model *model, double *buf, size_t count);
 GNP_API gnp_status gnp_params_set(gnp_model *model, const double *buf, size_t count);
 /* Same as gnp_params_set from a float64 device buffer, stream-ordered (no

@@ -134,6 +134,10 @@ class Model:
         th, pth = _host(params, np.float64)
         check(_lib.load().gnp_params_set(self._h, pth, th.size))
 
+    def set_scaling(self, on: bool):
+        """Eq. (6) scaling on (default) or off, the ablation (gnp_model_set_scaling)."""
+        check(_lib.load().gnp_model_set_scaling(self._h, 1 if on else 0))
+
     def apply(self, v: torch.Tensor, z: torch.Tensor | None = None, prec="f32", stream=None):
         """z = M(v); v of shape [n] or [n, nrhs] (node-major)."""
         p = PREC[prec]

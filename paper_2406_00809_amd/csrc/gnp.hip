@@ -79,7 +79,7 @@ template <typename IN>
 __global__ __launch_bounds__(BLOCK) void k_colnorm(int64_t n, int B, int64_t chunk,
                                                    const IN *__restrict__ v, double *partial,
                                                    unsigned *counter, double *tau,
-                                                   const int *__restrict__ skip) {
+                                                   const int *__restrict__ skip, int scaled) {
     if (skip && *skip) return;
     __shared__ double sh[BLOCK];
     const int t = threadIdx.x;
@@ -107,8 +107,8 @@ __global__ __launch_bounds__(BLOCK) void k_colnorm(int64_t n, int B, int64_t chu
             for (unsigned blk = 0; blk < gridDim.x; ++blk) a += partial[(int64_t)blk * B + t];
             const double tv = sqrt(a), sqn = sqrt((double)n);
             tau[3 * t] = tv;
-            tau[3 * t + 1] = tv > 0.0 ? sqn / tv : 0.0;
-            tau[3 * t + 2] = tv / sqn;
+            tau[3 * t + 1] = scaled ? (tv > 0.0 ? sqn / tv : 0.0) : 1.0;
+            tau[3 * t + 2] = scaled ? tv / sqn : 1.0;
         }
     }
 }
@@ -119,7 +119,7 @@ void launch_colnorm(gnp_model *m, const IN *v, int nrhs, double *tau_out, double
     const int64_t n = m->sys->n, chunk = colnorm_chunk(n);
     const int nb = grid_for(n, (int)chunk);
     hipLaunchKernelGGL(k_colnorm<IN>, dim3(nb), dim3(BLOCK), 0, st, n, nrhs, chunk, v, partial,
-                       counter, tau_out, skip);
+                       counter, tau_out, skip, m->scaled);
 }
 template void launch_colnorm<float>(gnp_model *, const float *, int, double *, double *,
                                     unsigned *, const int *, hipStream_t);
@@ -357,6 +357,13 @@ gnp_status gnp_model_create(gnp_system *sys, int L, int d, int h, const double *
 void gnp_model_destroy(gnp_model *model) { model_free(model); }
 
 size_t gnp_model_nparams(const gnp_model *model) { return model ? (size_t)model->np : 0; }
+
+gnp_status gnp_model_set_scaling(gnp_model *model, int on) {
+    if (!model) return fail(GNP_EINVAL, "null argument");
+    if (on != 0 && on != 1) return fail(GNP_EINVAL, "on must be 0 or 1");
+    model->scaled = on;
+    return GNP_OK;
+}
 
 gnp_status gnp_params_get(const gnp_model *m, double *buf, size_t count) {
     if (!m || !buf) return fail(GNP_EINVAL, "null argument");

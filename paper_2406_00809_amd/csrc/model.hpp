@@ -66,6 +66,7 @@ struct gnp_model {
     gnp_system *sys = nullptr;
     int L = 0, d = 0, h = 0;
     int64_t np = 0;
+    int scaled = 1;                // 0: without s, s^-1 of Eq. (6) (ablation)
     double *theta64 = nullptr;     // master parameters (device, float64)
     float *theta32 = nullptr;      // float32 copy (biases and vectors)
     uint16_t *pk_bf16 = nullptr;   // bf16 MFMA fragments
@@ -90,7 +91,8 @@ gnp_status model_workspace(gnp_model *m, int nrhs);
 int colnorm_blocks(int64_t n);
 
 // Column norms of v ([n][nrhs], float or double) into tau triples
-// (tau, sqrt(n)/tau, tau/sqrt(n)) at tau_out[3*k .. 3*k+2].
+// (tau, sqrt(n)/tau, tau/sqrt(n)) at tau_out[3*k .. 3*k+2]; (tau, 1, 1)
+// for a model without the scaling of Eq. (6).
 template <typename IN>
 void launch_colnorm(gnp_model *m, const IN *v, int nrhs, double *tau_out, double *partial,
                     unsigned *counter, const int *skip, hipStream_t st);

@@ -314,8 +314,8 @@ __global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__rest
 // spares a global reduction per Arnoldi step.  In a batch (gridDim.y
 // right-hand sides) block (0, 0) also records in *all_done whether every
 // right-hand side has ended its cycle (the network launches of the next step
-// are then skipped).
-__global__ void k_unit_tau(int64_t n, double *tau, const Ctl *ctl, int *all_done) {
+// are then skipped).  scaled = 0 (a network without Eq. (6)): (1, 1, 1).
+__global__ void k_unit_tau(int64_t n, double *tau, const Ctl *ctl, int *all_done, int scaled) {
     if (threadIdx.x != 0) return;
     if (all_done && blockIdx.y == 0) {
         int done = 1;
@@ -325,7 +325,7 @@ __global__ void k_unit_tau(int64_t n, double *tau, const Ctl *ctl, int *all_done
     ctl += blockIdx.y;
     if (ctl->cycle_done) return;
     tau += 3 * blockIdx.y;
-    const double tv = 1.0, sqn = sqrt((double)n);
+    const double tv = 1.0, sqn = scaled ? sqrt((double)n) : 1.0;
     tau[0] = tv;
     tau[1] = sqn / tv;
     tau[2] = tv / sqn;
@@ -781,8 +781,9 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
     // a float32/bfloat16 network as it reads w (it also stores v_j to vcur),
     // else by its own kernel at the end of step j - 1; with a basis of pitch
     // 32 that encoder also applies step j - 1's second correction w -= V h2,
-    // so that pass is not launched
-    const bool v_in_encoder = model && c->prec != GNP_F64;
+    // so that pass is not launched (the encoder takes the tau triple of Eq. (6),
+    // so a network without that scaling keeps the separate kernels)
+    const bool v_in_encoder = model && c->prec != GNP_F64 && model->scaled;
     const bool corr_in_encoder = v_in_encoder && MP == 32;
     // Jacobi: z_j = D^{-1} v_j; with any preconditioner z_j is kept in Z
     const bool jac = !model && c->precond == PRECOND_JACOBI;
@@ -792,7 +793,7 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                        c->ctl, 1, Bat{});
     if (model)
         hipLaunchKernelGGL(k_unit_tau, dim3(1), dim3(WAVE), 0, st, n, c->tau, c->ctl,
-                           (int *)nullptr);
+                           (int *)nullptr, model->scaled);
     for (int j = 0; j < nsteps; ++j) {
         KT *zj = flex ? Z + (int64_t)j * n : vcur;
         const bool fuse = v_in_encoder && j > 0;
@@ -849,7 +850,7 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                                (const KT *)w, vcur, c->ctl, 0, Bat{});
             if (model)
                 hipLaunchKernelGGL(k_unit_tau, dim3(1), dim3(WAVE), 0, st, n, c->tau, c->ctl,
-                                   (int *)nullptr);
+                                   (int *)nullptr, model->scaled);
         }
     }
     hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(BLOCK), 0, st, c->ctl, c->H, c->g, c->y, Bat{});
@@ -1063,7 +1064,7 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
     hipLaunchKernelGGL((k_normalize<float, double>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
                        (const double *)c->r, c->vpk, (const Ctl *)c->ctl, 1, bt);
     hipLaunchKernelGGL(k_unit_tau, dim3(1, nb), dim3(WAVE), 0, st, n, c->tau,
-                       (const Ctl *)c->ctl, c->all_done);
+                       (const Ctl *)c->ctl, c->all_done, model->scaled);
     for (int j = 0; j < nsteps; ++j) {
         float *zj = c->Zp + (int64_t)j * n * nb;
         GNP_TRY(forward_launch(model, c->prec, c->vpk, zj, nb, c->tau, c->act[0], c->act[1],
@@ -1089,7 +1090,7 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
         hipLaunchKernelGGL((k_normalize<float, float>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
                            (const float *)w, c->vpk, (const Ctl *)c->ctl, 0, bt);
         hipLaunchKernelGGL(k_unit_tau, dim3(1, nb), dim3(WAVE), 0, st, n, c->tau,
-                           (const Ctl *)c->ctl, c->all_done);
+                           (const Ctl *)c->ctl, c->all_done, model->scaled);
     }
     hipLaunchKernelGGL(k_backsolve, dim3(1, nb), dim3(BLOCK), 0, st, c->ctl, (const double *)c->H,
                        (const double *)c->g, c->y, bt);
