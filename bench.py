@@ -284,6 +284,10 @@ def main():
     ap.add_argument("--scale-ablation", action="store_true",
                     help="also train a network without the scaling of Eq. (6) (same initial "
                          "weights, steps and seed) and report its loss, iterations and solves/s")
+    ap.add_argument("--evolve", action="store_true",
+                    help="also run a sequence of convection-diffusion systems with a slowly "
+                         "growing Peclet number: per system the network as it is, then after "
+                         "200 fine-tuning steps from its weights; and one training from scratch")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the float32-network comparison solves")
     args = ap.parse_args()
@@ -568,6 +572,57 @@ def main():
         abl["with_scaling_iter_auc"] = api.auc(hh1, 1e-8)[0]
         extra["without_eq6_scaling"] = abl
         log(f"network without Eq. (6) scaling: {abl}")
+
+    if args.evolve:
+        # continual fine-tuning over evolving systems (Sec. 5): the C2 pattern
+        # with Pe 10 -> 20; the trained network is carried along, the system
+        # updated in place with gnp_system_set_values, and the network tuned
+        # for 200 steps per system (Adam, lr 1e-4; the best-loss step is kept,
+        # so a run whose loss never drops below its first step's leaves the
+        # weights as they were)
+        M4 = api.Model(S, L, d, h, th)
+        ev = []
+        tune = 200
+
+        def timed_solve(mdl, bb):
+            xx = torch.zeros(S.n, dtype=torch.float64, device=dev)
+            api.fgmres_solve(S, bb, mdl, x=xx, m=m, rtol=1e-8, maxiters=args.maxiters,
+                             prec=args.prec, want_hist=False)
+            xx.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, inf, _ = api.fgmres_solve(S, bb, mdl, x=xx, m=m, rtol=1e-8,
+                                         maxiters=args.maxiters, prec=args.prec, want_hist=False)
+            torch.cuda.synchronize()
+            return inf, time.perf_counter() - t1
+
+        for pe in (12.5, 15.0, 17.5, 20.0):
+            At = I.convdiff3d(N, pe)
+            S.set_values(At.val)
+            bt = S.spmv(ones, prec="f64")
+            inf0, _ = timed_solve(M4, bt)
+            t1 = time.perf_counter()
+            ht, bst = M4.train(tune, 32, lr=1e-4, seed=3, prec="f32")
+            torch.cuda.synchronize()
+            tt = time.perf_counter() - t1
+            inf1, s1 = timed_solve(M4, bt)
+            ev.append({"Pe": pe, "iters_as_is": inf0["iters"], "iters_tuned": inf1["iters"],
+                       "converged_tuned": inf1["converged"], "tune_steps": tune, "tune_s": tt,
+                       "tune_loss_first_best": [float(ht[0]), float(ht[bst])],
+                       "tune_best_step": int(bst), "tuned_solves_per_s": 1.0 / s1})
+            log(f"Pe {pe}: {ev[-1]}")
+        M5 = api.Model(S, L, d, h, th0)
+        t1 = time.perf_counter()
+        M5.train(args.train_steps, 32, lr=1e-3, seed=2, prec="f32")
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t1
+        inf5, s5 = timed_solve(M5, bt)
+        extra["evolving_systems"] = {
+            "sequence": ev,
+            "from_scratch_at_last": {"train_steps": args.train_steps, "train_s": ts,
+                                     "iters": inf5["iters"], "solves_per_s": 1.0 / s5}}
+        # restore the benchmark system
+        S.set_values(A.val)
 
     # ---- dominant kernel: one Res-GCONV layer, same launch configuration
     lay_ms = M.time_layer(nrhs=1, prec=args.prec, reps=200)

@@ -84,6 +84,21 @@ GNP_API const char *gnp_version(void);
 GNP_API gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr,
                                      const int32_t *colind, const double *val, int prescale,
                                      void *hip_stream, gnp_system **out);
+
+/* Replace the values of a system's matrix, keeping its sparsity pattern: the
+ * slowly evolving systems for which the paper proposes to keep training the
+ * same network (Sec. 5, "Discussions and Conclusions").  val: host array of nnz
+ * values in the CSR order of gnp_system_create.  Everything that follows from
+ * the values is made again on the device exactly as gnp_system_create makes
+ * it (gamma, the prescaled A and A-hat of Eq. (4) in every precision, their
+ * transposes), so the system then equals one created from the new values.
+ * Networks of the system stay valid and keep their weights (training
+ * continues from them); the Jacobi diagonal is made again on its next use.
+ * No solve, training run or server request may be in flight on the system.
+ * Errors: GNP_EINVAL for a null system or val, a non-finite value, or
+ * values whose gamma would be zero or not finite; the system is then
+ * unchanged. */
+GNP_API gnp_status gnp_system_set_values(gnp_system *sys, const double *val, void *hip_stream);
 GNP_API void gnp_system_destroy(gnp_system *sys);
 
 /* gamma of the input matrix, and gamma of the matrix after the optional

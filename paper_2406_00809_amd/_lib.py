@@ -67,6 +67,7 @@ SIGNATURES = {
     "gnp_spmv": (C.c_int, [VP, VP, VP, C.c_int, VP]),
     "gnp_model_create": (C.c_int, [VP, C.c_int, C.c_int, C.c_int, VP, C.POINTER(VP)]),
     "gnp_model_destroy": (None, [VP]),
+    "gnp_system_set_values": (C.c_int, [VP, VP, VP]),
     "gnp_model_nparams": (C.c_size_t, [VP]),
     "gnp_model_set_scaling": (C.c_int, [VP, C.c_int]),
     "gnp_params_get": (C.c_int, [VP, VP, C.c_size_t]),

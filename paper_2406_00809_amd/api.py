@@ -66,6 +66,17 @@ class System:
     def handle(self):
         return self._h
 
+    def set_values(self, val, stream=None):
+        """New values on the same pattern (gnp_system_set_values)."""
+        v, pv = _host(val, np.float64)
+        if v.size != self.nnz:
+            raise ValueError("val must have nnz entries")
+        L = _lib.load()
+        check(L.gnp_system_set_values(self._h, pv, _stream(stream)))
+        g0, g1 = C.c_double(), C.c_double()
+        check(L.gnp_system_gamma(self._h, C.byref(g0), C.byref(g1)))
+        self.gamma_input, self.gamma = g0.value, g1.value
+
     def export(self):
         L = _lib.load()
         val = np.empty(self.nnz)

@@ -170,6 +170,8 @@ struct gnp_system {
     float *ahat32 = nullptr;
     uint16_t *ahat16 = nullptr;                  // A-hat in bfloat16 (the BF16 network)
     int32_t *trp = nullptr, *tci = nullptr;      // CSR of A^T
+    int32_t *tperm = nullptr;                    // entry k of A^T is entry tperm[k] of A
+    int prescale = 0;                            // A was divided by its own gamma
     double *tval64 = nullptr;                    // A^T
     float *tval32 = nullptr;
     double *tahat64 = nullptr;                   // A-hat^T

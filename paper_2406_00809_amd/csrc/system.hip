@@ -183,7 +183,7 @@ static void sys_free(gnp_system *s) {
     if (!s) return;
     void *ptrs[] = {s->rp,     s->ci,      s->val64,  s->val32,   s->ahat64,  s->ahat32,
                     s->trp,    s->tci,     s->tval64, s->tval32,  s->tahat64, s->tahat32,
-                    s->ahat16,   s->counters, s->scratch, s->dinv64};
+                    s->ahat16,   s->counters, s->scratch, s->dinv64, s->tperm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     solve_cache_free(s->solve_cache);
@@ -227,6 +227,30 @@ static gnp_status validate_csr(int64_t n, int64_t nnz, const int32_t *rp, const 
     return GNP_OK;
 }
 
+// Finite values, and finite, nonzero absolute row and column sums (so that
+// gamma of the input and of the prescaled matrix is finite and positive).
+static gnp_status validate_values(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                                  const double *val) {
+    if (!val) return fail(GNP_EINVAL, "null value array");
+    std::vector<double> col(n, 0.0);
+    double rmax = 0.0, cmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double r = 0.0;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (!std::isfinite(val[k]))
+                return fail(GNP_EINVAL, "non-finite value at nnz " + std::to_string(k));
+            r += fabs(val[k]);
+            col[ci[k]] += fabs(val[k]);
+        }
+        rmax = r > rmax ? r : rmax;
+    }
+    for (int64_t j = 0; j < n; ++j) cmax = col[j] > cmax ? col[j] : cmax;
+    (void)nnz;
+    if (!(rmax > 0.0) || !std::isfinite(rmax) || !std::isfinite(cmax))
+        return fail(GNP_EINVAL, "gamma is zero or not finite (all-zero matrix?)");
+    return GNP_OK;
+}
+
 static gnp_status gamma_dev(gnp_system *s, const double *val, double *g_dev,
                             unsigned long long *maxes, hipStream_t st) {
     GNP_HIP(hipMemsetAsync(maxes, 0, 2 * sizeof(unsigned long long), st));
@@ -250,6 +274,54 @@ const char *gnp_last_error(void) { return g_err.c_str(); }
 
 const char *gnp_version(void) { return "libgnp 0.1 (gfx950)"; }
 
+}  // extern "C"
+
+namespace gnp {
+// Everything on the device that follows from the values (input values on
+// the device in tmp64, the transposed pattern already built): gamma of the
+// input, the (prescaled) A and its transpose in float64/float32, gamma of
+// that matrix, A-hat in three precisions and its transpose.  gam: 2
+// doubles, maxes: 2 words of device scratch.  Waits for the stream.
+static gnp_status derive_values(gnp_system *s, double *tmp64, double *gam,
+                                unsigned long long *maxes, hipStream_t st) {
+    const int64_t nnz = s->nnz;
+    const int gk = grid_for(nnz, BLOCK);
+    hipLaunchKernelGGL(k_gather, dim3(gk), dim3(BLOCK), 0, st, nnz, s->tperm, tmp64, s->tval64,
+                       s->tval32);
+    GNP_TRY(gamma_dev(s, tmp64, gam, maxes, st));
+    if (s->prescale) {
+        hipLaunchKernelGGL(k_div, dim3(gk), dim3(BLOCK), 0, st, nnz, tmp64, gam, s->val64,
+                           s->val32);
+        hipLaunchKernelGGL(k_gather, dim3(gk), dim3(BLOCK), 0, st, nnz, s->tperm, s->val64,
+                           s->tval64, s->tval32);
+        GNP_TRY(gamma_dev(s, s->val64, gam + 1, maxes, st));
+    } else {
+        GNP_HIP(hipMemcpyAsync(s->val64, tmp64, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
+                               st));
+        hipLaunchKernelGGL(k_to_f32, dim3(gk), dim3(BLOCK), 0, st, nnz, s->val64, s->val32);
+        GNP_HIP(hipMemcpyAsync(gam + 1, gam, sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    // A-hat = A / gamma and its transpose
+    hipLaunchKernelGGL(k_div, dim3(gk), dim3(BLOCK), 0, st, nnz, s->val64, gam + 1, s->ahat64,
+                       s->ahat32);
+    hipLaunchKernelGGL(k_to_bf16, dim3(gk), dim3(BLOCK), 0, st, nnz, (const float *)s->ahat32,
+                       s->ahat16);
+    hipLaunchKernelGGL(k_gather, dim3(gk), dim3(BLOCK), 0, st, nnz, s->tperm, s->ahat64,
+                       s->tahat64, s->tahat32);
+    GNP_HIP(hipGetLastError());
+    double gh[2];
+    GNP_HIP(hipMemcpyAsync(gh, gam, sizeof(gh), hipMemcpyDeviceToHost, st));
+    GNP_HIP(hipStreamSynchronize(st));
+    s->gamma_raw = gh[0];
+    s->gamma = gh[1];
+    if (!(gh[0] > 0.0) || !(gh[1] > 0.0) || !std::isfinite(gh[1]))
+        return fail(GNP_EINVAL, "gamma is zero or not finite (all-zero matrix?)");
+    return GNP_OK;
+}
+}  // namespace gnp
+
+extern "C" {
+
 gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colind,
                              const double *val, int prescale, void *hip_stream,
                              gnp_system **out) {
@@ -257,12 +329,14 @@ gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr, cons
     *out = nullptr;
     int max_row = 0;
     GNP_TRY(validate_csr(n, nnz, rowptr, colind, val, &max_row));
+    GNP_TRY(validate_values(n, nnz, rowptr, colind, val));
     hipStream_t st = (hipStream_t)hip_stream;
     gnp_system *s = new gnp_system();
     s->n = n;
     s->nnz = nnz;
     s->max_row = max_row;
-    int32_t *cnt = nullptr, *tperm = nullptr, *scan_tmp = nullptr;
+    s->prescale = prescale ? 1 : 0;
+    int32_t *cnt = nullptr, *scan_tmp = nullptr;
     double *tmp64 = nullptr, *gam = nullptr;
     unsigned long long *maxes = nullptr;
     gnp_status rc = GNP_OK;
@@ -284,7 +358,7 @@ gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr, cons
         s->nscratch = 4096;
         GNP_TRY(dalloc(&s->scratch, s->nscratch));
         GNP_TRY(dalloc(&cnt, n + 1));
-        GNP_TRY(dalloc(&tperm, nnz));
+        GNP_TRY(dalloc(&s->tperm, nnz));
         GNP_TRY(dalloc(&scan_tmp, 2 * (n / SCAN_PER_BLOCK + 16)));
         GNP_TRY(dalloc(&tmp64, nnz));
         GNP_TRY(dalloc(&gam, 2));
@@ -300,43 +374,13 @@ gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr, cons
         GNP_TRY(scan_inclusive(cnt, n + 1, scan_tmp, st));
         GNP_HIP(hipMemcpyAsync(s->trp, cnt, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_fill_transpose, dim3(gn), dim3(BLOCK), 0, st, n, s->rp, s->ci, cnt,
-                           s->tci, tperm);
-        hipLaunchKernelGGL(k_sort_segments, dim3(gn), dim3(BLOCK), 0, st, n, s->trp, s->tci, tperm);
-        // gamma of the input matrix
-        hipLaunchKernelGGL(k_gather, dim3(gk), dim3(BLOCK), 0, st, nnz, tperm, tmp64, s->tval64,
-                           s->tval32);
-        GNP_TRY(gamma_dev(s, tmp64, gam, maxes, st));
-        if (prescale) {
-            hipLaunchKernelGGL(k_div, dim3(gk), dim3(BLOCK), 0, st, nnz, tmp64, gam, s->val64,
-                               s->val32);
-            hipLaunchKernelGGL(k_gather, dim3(gk), dim3(BLOCK), 0, st, nnz, tperm, s->val64,
-                               s->tval64, s->tval32);
-            GNP_TRY(gamma_dev(s, s->val64, gam + 1, maxes, st));
-        } else {
-            GNP_HIP(hipMemcpyAsync(s->val64, tmp64, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
-                                   st));
-            hipLaunchKernelGGL(k_to_f32, dim3(gk), dim3(BLOCK), 0, st, nnz, s->val64, s->val32);
-            GNP_HIP(hipMemcpyAsync(gam + 1, gam, sizeof(double), hipMemcpyDeviceToDevice, st));
-        }
-        // A-hat = A / gamma and its transpose
-        hipLaunchKernelGGL(k_div, dim3(gk), dim3(BLOCK), 0, st, nnz, s->val64, gam + 1, s->ahat64,
-                           s->ahat32);
-        hipLaunchKernelGGL(k_to_bf16, dim3(gk), dim3(BLOCK), 0, st, nnz, (const float *)s->ahat32,
-                           s->ahat16);
-        hipLaunchKernelGGL(k_gather, dim3(gk), dim3(BLOCK), 0, st, nnz, tperm, s->ahat64,
-                           s->tahat64, s->tahat32);
-        GNP_HIP(hipGetLastError());
-        double gh[2];
-        GNP_HIP(hipMemcpyAsync(gh, gam, sizeof(gh), hipMemcpyDeviceToHost, st));
-        GNP_HIP(hipStreamSynchronize(st));
-        s->gamma_raw = gh[0];
-        s->gamma = gh[1];
-        if (!(gh[0] > 0.0) || !(gh[1] > 0.0) || !std::isfinite(gh[1]))
-            return fail(GNP_EINVAL, "gamma is zero or not finite (all-zero matrix?)");
-        return GNP_OK;
+                           s->tci, s->tperm);
+        hipLaunchKernelGGL(k_sort_segments, dim3(gn), dim3(BLOCK), 0, st, n, s->trp, s->tci,
+                           s->tperm);
+        return derive_values(s, tmp64, gam, maxes, st);
     };
     rc = run();
-    void *tmps[] = {cnt, tperm, scan_tmp, tmp64, gam, maxes};
+    void *tmps[] = {cnt, scan_tmp, tmp64, gam, maxes};
     for (void *p : tmps)
         if (p) (void)hipFree(p);
     if (rc != GNP_OK) {
@@ -345,6 +389,34 @@ gnp_status gnp_system_create(int64_t n, int64_t nnz, const int32_t *rowptr, cons
     }
     *out = s;
     return GNP_OK;
+}
+
+gnp_status gnp_system_set_values(gnp_system *sys, const double *val, void *hip_stream) {
+    if (!sys) return fail(GNP_EINVAL, "null system");
+    std::vector<int32_t> rp(sys->n + 1), ci(sys->nnz);
+    GNP_HIP(hipMemcpy(rp.data(), sys->rp, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost));
+    GNP_HIP(hipMemcpy(ci.data(), sys->ci, sizeof(int32_t) * ci.size(), hipMemcpyDeviceToHost));
+    GNP_TRY(validate_values(sys->n, sys->nnz, rp.data(), ci.data(), val));
+    hipStream_t st = (hipStream_t)hip_stream;
+    double *tmp64 = nullptr, *gam = nullptr;
+    unsigned long long *maxes = nullptr;
+    auto run = [&]() -> gnp_status {
+        GNP_TRY(dalloc(&tmp64, sys->nnz));
+        GNP_TRY(dalloc(&gam, 2));
+        GNP_TRY(dalloc(&maxes, 2));
+        GNP_HIP(hipMemcpyAsync(tmp64, val, sizeof(double) * sys->nnz, hipMemcpyHostToDevice, st));
+        if (sys->dinv64) {  // the Jacobi diagonal is made again on its next use
+            GNP_HIP(hipStreamSynchronize(st));
+            GNP_HIP(hipFree(sys->dinv64));
+            sys->dinv64 = nullptr;
+        }
+        return derive_values(sys, tmp64, gam, maxes, st);
+    };
+    const gnp_status rc = run();
+    void *tmps[] = {tmp64, gam, maxes};
+    for (void *p : tmps)
+        if (p) (void)hipFree(p);
+    return rc;
 }
 
 void gnp_system_destroy(gnp_system *sys) { sys_free(sys); }
