@@ -288,6 +288,9 @@ def main():
                     help="also run a sequence of convection-diffusion systems with a slowly "
                          "growing Peclet number: per system the network as it is, then after "
                          "200 fine-tuning steps from its weights; and one training from scratch")
+    ap.add_argument("--inner-outer-only", action="store_true",
+                    help="only time inner-outer GMRES on the benchmark system (outer FGMRES(10), "
+                         "inner GMRES(10) to 1e-6, FP32), for a kernel profile of that method")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the float32-network comparison solves")
     args = ap.parse_args()
@@ -314,6 +317,23 @@ def main():
     th0 = I.init_params(L, d, h, 12)
     M = api.Model(S, L, d, h, th0)
     log(f"system n={S.n} nnz={S.nnz} gamma={S.gamma_input:.6f}")
+    if args.inner_outer_only:
+        ones = torch.ones(S.n, dtype=torch.float64, device=dev)
+        b = S.spmv(ones, prec="f64")
+        x = torch.zeros(S.n, dtype=torch.float64, device=dev)
+        for k in range(args.warmup + args.steps):
+            if k == args.warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            x.zero_()
+            _, inf, _ = api.fgmres_solve_gmres(S, b, x=x, m=10, rtol=1e-8, maxiters=args.maxiters,
+                                               inner_k=10, inner_tol=1e-6, prec="f32",
+                                               want_hist=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"inner_outer_solves_per_s": args.steps / el, "outer_iters": inf["iters"],
+                          "rel_res_true": inf["rel_res_true"], "steps": args.steps}), flush=True)
+        return
     if args.kernels_only:
         v = torch.randn(S.n, dtype=torch.float32, device=dev)
         M.apply(v, prec=args.prec)
