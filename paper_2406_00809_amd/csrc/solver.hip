@@ -7,7 +7,7 @@
 // v_{j+1} = w / h_{j+1,j}.  With a float32/bfloat16 network the next step's
 // encoder does the normalisation, and with a basis pitch of 32 also pass 2,
 // as it reads w; the network takes tau = 1 for every basis vector (unit norm,
-// Eq. (6)).
+// Eq. (6)).  Otherwise pass 2 writes v_{j+1} itself.
 //
 // Layout: the Arnoldi basis is stored row-interleaved, V[i * MP + k]
 // (MP = m + 1 rounded up to a multiple of 32), so that the j + 1 basis
@@ -289,9 +289,10 @@ __global__ __launch_bounds__(BLOCK) void k_inner_end(int64_t n, const double *__
 // ---------------------------------------------------------------------------
 // v = src / div into vcur (contiguous), div = beta (cycle start) or
 // h_{j+1,j}.  The basis column of v is written by the next step's first
-// Gram-Schmidt pass, which reads that row of the basis anyway.  (With a
-// float32/bfloat16 network the encoder does this division itself for
-// j >= 1, with the same expression.)
+// Gram-Schmidt pass, which reads that row of the basis anyway.  (For j >= 1
+// of a single solve the division is done with the same expression by the
+// encoder of a float32/bfloat16 network, else by the third Gram-Schmidt
+// pass.)
 // ---------------------------------------------------------------------------
 template <typename KT, typename ST>
 __global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__restrict__ src,
@@ -337,6 +338,8 @@ __global__ void k_unit_tau(int64_t n, double *tau, const Ctl *ctl, int *all_done
 // column j (v_j) is taken from vcur and stored into the basis here.
 // MODE 1: w -= V_j hprev, then dots and ||w||^2 of the updated w.  MODE 2:
 // w -= V_j hprev only (its norm follows from MODE 1's sums, k_fin_givens).
+// MODE 3 (one right-hand side): MODE 2, and the next basis vector
+// v_{j+1} = w / h_{j+1,j} into vout with the expression of k_normalize.
 // Entries k > j are masked by selection (they may hold an older cycle).
 // ---------------------------------------------------------------------------
 template <typename KT> struct Quad;
@@ -360,9 +363,11 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                                                const double *__restrict__ hprev,
                                                double *__restrict__ partial, int pstride,
                                                const Ctl *ctl, Bat bt,
-                                               const KT *__restrict__ vcur) {
+                                               const KT *__restrict__ vcur,
+                                               KT *__restrict__ vout) {
     ctl += blockIdx.y;
     if (ctl->cycle_done) return;
+    const double hdiv = MODE == 3 ? ctl->hnext : 1.0;
     V += blockIdx.y * bt.basis;
     w += blockIdx.y * bt.vec;
     if (MODE == 0) vcur += blockIdx.y;
@@ -433,6 +438,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                 corr += __shfl_xor(corr, 4, WAVE);
                 const KT wn = (KT)((double)wold[ru] - corr);
                 if (ok && q == 0) w[i] = wn;
+                if (MODE == 3 && ok && q == 0) vout[i] = (KT)((double)wn / hdiv);
                 wi = ok ? (double)wn : 0.0;
             }
             if (MODE <= 1) {
@@ -442,7 +448,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
             if (MODE <= 1 && q == 0) nrm += wi * wi;
         }
     }
-    if constexpr (MODE == 2) return;  // no sums
+    if constexpr (MODE >= 2) return;  // no sums
     __shared__ double sh[BLOCK / WAVE][8 * NA + 1];
     const int lane = t % WAVE, wv = t / WAVE;
     if (MODE <= 1) {
@@ -832,22 +838,24 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                                 s->max_row);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
-                           Bat{}, (const KT *)vcur);
+                           Bat{}, (const KT *)vcur, (KT *)nullptr);
         hipLaunchKernelGGL(k_fin_dots, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, Bat{});
         hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)c->h1, c->partial, pstride, (const Ctl *)c->ctl,
-                           Bat{}, (const KT *)nullptr);
+                           Bat{}, (const KT *)nullptr, (KT *)nullptr);
         hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
                            c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, Bat{}, c->tstamp);
-        if (!corr_in_encoder)
+        if (!v_in_encoder)  // third pass and v_{j+1} = w / h_{j+1,j} in one kernel
+            hipLaunchKernelGGL((k_cgs<KT, MP, 3>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j,
+                               w, (const double *)c->h2, c->partial, pstride,
+                               (const Ctl *)c->ctl, Bat{}, (const KT *)nullptr, vcur);
+        else if (!corr_in_encoder)
             hipLaunchKernelGGL((k_cgs<KT, MP, 2>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j,
                                w, (const double *)c->h2, c->partial, pstride,
-                               (const Ctl *)c->ctl, Bat{}, (const KT *)nullptr);
+                               (const Ctl *)c->ctl, Bat{}, (const KT *)nullptr, (KT *)nullptr);
         if (!v_in_encoder) {
-            hipLaunchKernelGGL((k_normalize<KT, KT>), dim3(sg), dim3(BLOCK), 0, st, n,
-                               (const KT *)w, vcur, c->ctl, 0, Bat{});
             if (model)
                 hipLaunchKernelGGL(k_unit_tau, dim3(1), dim3(WAVE), 0, st, n, c->tau, c->ctl,
                                    (int *)nullptr, model->scaled);
@@ -1074,19 +1082,19 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
                                          (int)(sizeof(Ctl) / sizeof(int)), s->max_row);
         hipLaunchKernelGGL((k_cgs<float, MP, 0>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
-                           bt, (const float *)c->vpk);
+                           bt, (const float *)c->vpk, (float *)nullptr);
         hipLaunchKernelGGL(k_fin_dots, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, bt);
         hipLaunchKernelGGL((k_cgs<float, MP, 1>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)c->h1, c->partial, pstride, (const Ctl *)c->ctl,
-                           bt, (const float *)nullptr);
+                           bt, (const float *)nullptr, (float *)nullptr);
         hipLaunchKernelGGL(k_fin_givens, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
                            c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, bt,
                            (uint64_t *)nullptr);
         hipLaunchKernelGGL((k_cgs<float, MP, 2>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)c->h2, c->partial, pstride, (const Ctl *)c->ctl,
-                           bt, (const float *)nullptr);
+                           bt, (const float *)nullptr, (float *)nullptr);
         hipLaunchKernelGGL((k_normalize<float, float>), dim3(sg, nb), dim3(BLOCK), 0, st, n,
                            (const float *)w, c->vpk, (const Ctl *)c->ctl, 0, bt);
         hipLaunchKernelGGL(k_unit_tau, dim3(1, nb), dim3(WAVE), 0, st, n, c->tau,
