@@ -152,3 +152,28 @@ def test_c2_batched_cycle_equals_single_solves(api, c2):
                                       maxiters=30, prec="bf16", want_hist=False)
         assert infos[k]["iters"] == info["iters"] == 30
         assert np.array_equal(Xh[k], x.cpu().numpy()), k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_c2_inner_outer_gmres(api, c2, prec):
+    """Inner-outer GMRES (outer FGMRES(10), inner GMRES(10) to 1e-6) at full
+    size against the oracle's: FP64 with the same outer steps, residual
+    history 1e-8 and x element by element; FP32 converging within the
+    iteration bar to a host-checked true residual."""
+    import torch
+    A, S, M, ref, th = c2
+    b = A.to_scipy() @ np.ones(A.n) / S.gamma_input
+    x, info, hist = api.fgmres_solve_gmres(S, _dev(b, torch.float64), m=10, rtol=1e-8,
+                                           maxiters=300, inner_k=10, inner_tol=1e-6, prec=prec)
+    r = O.fgmres(ref, b, 10, 1e-8, 300, M="gmres", inner=(10, 1e-6), ortho=O.CGS2)
+    print(prec, "gpu", info, "oracle", r["info"])
+    assert info["converged"] == 1 and r["info"]["converged"] == 1
+    xs = x.cpu().numpy()
+    true = np.linalg.norm(b - ref.A.to_scipy() @ xs) / np.linalg.norm(b)
+    assert true <= 1e-8
+    if prec == "f64":
+        assert info["iters"] == r["info"]["iters"]
+        np.testing.assert_allclose(hist, r["hist"], rtol=1e-8)
+        np.testing.assert_allclose(xs, r["x"], rtol=0, atol=1e-7 * np.abs(r["x"]).max())
+    else:
+        assert _iters_close(info["iters"], r["info"]["iters"])
