@@ -242,6 +242,18 @@ GNP_API gnp_status fgmres_solve_gmres(gnp_system *sys, const double *b_dev, doub
                                       gnp_solve_info *info, void *hip_stream);
 
 
+/* Time limit for the single solves on this system (fgmres_solve,
+ * fgmres_solve_jacobi, fgmres_solve_gmres), the stopping criterion the paper
+ * uses for its time comparisons besides rtol (Sec. 3, "Stopping criteria"):
+ * once the initial residual is known the device takes a deadline `seconds`
+ * later on its own wall clock; the first Arnoldi step that ends after it
+ * ends the cycle, x is updated, and the solve returns with converged = 0
+ * unless that cycle reached rtol.  maxiters still bounds the steps.  0 (the
+ * default) means no limit.  Served requests and the sampler are not
+ * affected.  Errors: GNP_EINVAL for a null system or a negative or
+ * non-finite value. */
+GNP_API gnp_status gnp_system_set_timeout(gnp_system *sys, double seconds);
+
 /* Elapsed wall-clock time of the last single solve on this system
  * (fgmres_solve, fgmres_solve_jacobi or fgmres_solve_gmres), for the
  * Time-AUC metric of Sec. 3 ("Evaluation metrics"): t_host[i] = seconds from

@@ -84,6 +84,7 @@ SIGNATURES = {
     "fgmres_solve_gmres": (C.c_int, [VP, VP, VP, C.c_int, C.c_double, C.c_int, C.c_int,
                                      C.c_double, C.c_int, VP, C.POINTER(SolveInfo), VP]),
     "fgmres_step_times": (C.c_int, [VP, VP, C.c_int]),
+    "gnp_system_set_timeout": (C.c_int, [VP, C.c_double]),
     "gnp_auc": (C.c_int, [VP, VP, C.c_int, C.c_double, VP, VP]),
     "gnp_train": (C.c_int, [VP, C.POINTER(TrainOpts), VP, VP, C.POINTER(C.c_int), VP]),
     "gnp_loss_grad": (C.c_int, [VP, VP, C.c_int, C.c_int, F64P, VP, VP]),

@@ -66,6 +66,11 @@ class System:
     def handle(self):
         return self._h
 
+    def set_timeout(self, seconds: float):
+        """Time limit of every later single solve on this system, 0 = none
+        (gnp_system_set_timeout)."""
+        check(_lib.load().gnp_system_set_timeout(self._h, float(seconds)))
+
     def set_values(self, val, stream=None):
         """New values on the same pattern (gnp_system_set_values)."""
         v, pv = _host(val, np.float64)

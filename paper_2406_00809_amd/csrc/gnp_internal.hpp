@@ -181,6 +181,7 @@ struct gnp_system {
     double *scratch = nullptr;                   // small reduction scratch
     int nscratch = 0;
     double *dinv64 = nullptr;                    // 1 / a_ii (Jacobi preconditioner), made on first use
+    double solve_timeout = 0.0;                  // seconds per single solve, 0 = none
     void *solve_cache = nullptr;                 // FGMRES workspace of fgmres_solve
     void *batch_cache = nullptr;                 // workspace of fgmres_solve_batch
 };

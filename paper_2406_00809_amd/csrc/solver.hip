@@ -167,7 +167,9 @@ __global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *
         ctl->beta = beta;
         if (initial) {
             if (hist) hist[0] = rel;
-            if (tstamp) tstamp[0] = (uint64_t)wall_clock64();
+            const uint64_t now = (uint64_t)wall_clock64();
+            if (tstamp) tstamp[0] = now;
+            if (ctl->timeout_ticks) ctl->deadline = now + ctl->timeout_ticks;
             ctl->est_rel = rel;
         }
         if (!isfinite(beta)) {
@@ -175,6 +177,8 @@ __global__ __launch_bounds__(BLOCK) void k_fin_residual(int nblk, const double *
             ctl->solve_done = 1;
         } else if (beta <= ctl->target) {
             ctl->converged = 1;
+            ctl->solve_done = 1;
+        } else if (ctl->timed_out) {
             ctl->solve_done = 1;
         } else if (ctl->it >= ctl->maxiters) {
             ctl->solve_done = 1;
@@ -583,6 +587,10 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const dou
             ctl->hnext = hn;
             if (est <= ctl->target || j + 1 >= m || ctl->it >= ctl->maxiters) ctl->cycle_done = 1;
         }
+        if (ctl->deadline && (uint64_t)wall_clock64() >= ctl->deadline) {
+            ctl->timed_out = 1;
+            ctl->cycle_done = 1;
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= j + 1; i += BLOCK) H[(int64_t)i * m + j] = col[i];
@@ -912,6 +920,14 @@ gnp_status solve_begin(SolveCtx *c, const double *b, const double *x, int m, dou
     memset(&init, 0, sizeof(init));
     init.m = m;
     init.maxiters = maxiters;
+    if (c->timeout_s > 0.0) {
+        int dev = 0, khz = 0;
+        GNP_HIP(hipGetDevice(&dev));
+        GNP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        if (khz <= 0) return fail(GNP_EDEVICE, "device reports no wall-clock rate");
+        const double ticks = c->timeout_s * 1e3 * (double)khz;
+        init.timeout_ticks = ticks < 1.0 ? 1 : ticks > 1e18 ? (uint64_t)1e18 : (uint64_t)ticks;
+    }
     *c->ctl_host = init;
     GNP_HIP(hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
     const int sg = stream_grid(n);
@@ -1225,6 +1241,7 @@ extern "C" gnp_status fgmres_solve(gnp_system *sys, gnp_model *model, const doub
     SolveCtx *c = (SolveCtx *)sys->solve_cache;
     GNP_TRY(solve_ctx_prepare(c, sys, m, maxiters, prec, model ? model->d : 0));
     c->prec = prec;
+    c->timeout_s = sys->solve_timeout;
     return solve_run(c, model, b_dev, x_dev, m, rtol, maxiters, hist, info,
                      (hipStream_t)hip_stream);
 }
@@ -1276,6 +1293,7 @@ extern "C" gnp_status fgmres_solve_jacobi(gnp_system *sys, const double *b_dev, 
     SolveCtx *c = (SolveCtx *)sys->solve_cache;
     GNP_TRY(solve_ctx_prepare(c, sys, m, maxiters, prec, 0));
     c->prec = prec;
+    c->timeout_s = sys->solve_timeout;
     c->precond = PRECOND_JACOBI;
     const gnp_status r = solve_run(c, nullptr, b_dev, x_dev, m, rtol, maxiters, hist, info, st);
     c->precond = PRECOND_MODEL;
@@ -1307,10 +1325,19 @@ extern "C" gnp_status fgmres_solve_gmres(gnp_system *sys, const double *b_dev, d
     if (!c->inner_x) GNP_HIP(hipMalloc(&c->inner_x, sizeof(double) * sys->n));
     c->inner_k = inner_k;
     c->inner_tol = inner_tol;
+    c->timeout_s = sys->solve_timeout;
     c->precond = PRECOND_GMRES;
     const gnp_status r = solve_run(c, nullptr, b_dev, x_dev, m, rtol, maxiters, hist, info, st);
     c->precond = PRECOND_MODEL;
     return r;
+}
+
+extern "C" gnp_status gnp_system_set_timeout(gnp_system *sys, double seconds) {
+    if (!sys) return fail(GNP_EINVAL, "null system");
+    if (!(seconds >= 0.0) || !std::isfinite(seconds))
+        return fail(GNP_EINVAL, "seconds must be finite and >= 0");
+    sys->solve_timeout = seconds;
+    return GNP_OK;
 }
 
 extern "C" gnp_status fgmres_step_times(gnp_system *sys, double *t_host, int count) {

@@ -20,6 +20,11 @@ struct Ctl {
     int solve_done;
     int m, maxiters, pad_;
     double bnorm, target, beta, est, rel_true, wnorm0, hnext, est_rel;
+    // time limit (the paper's timeout criterion): 0 = none; the deadline is
+    // set on the device when r_0 is known, and a step that ends after it
+    // ends the solve
+    uint64_t timeout_ticks, deadline;
+    int timed_out, pad2_;
 };
 
 // Per-right-hand-side strides (elements) of a batched solve: right-hand
@@ -76,6 +81,7 @@ struct SolveCtx {
     double *inner_x = nullptr;
     int inner_k = 0;
     double inner_tol = 0.0;
+    double timeout_s = 0.0;  // time limit of the next solve_begin (0: none)
 };
 
 gnp_status solve_ctx_prepare(SolveCtx *c, gnp_system *sys, int m, int maxiters,

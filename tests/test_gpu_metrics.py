@@ -74,3 +74,42 @@ def test_step_times_follow_every_single_solve_kind(api):
         api.fgmres_step_times(api.System(I.laplace2d(4)), 1)
     with pytest.raises(GNPError):
         api.auc([1.0, 0.1], 0.0)
+
+
+def test_timeout_stops_the_solve(api):
+    """The time limit of Sec. 3's time comparisons (gnp_system_set_timeout):
+    a generous limit leaves the solve bit-identical, a tiny one stops it
+    after one step, and half the unlimited solve's time stops it at the
+    first step whose end lies past the limit."""
+    from paper_2406_00809_amd._lib import GNPError
+    A = I.laplace2d(48)
+    S = api.System(A)
+    bd = _dev(I.rhs_normal(A.n, 23))
+    kw = dict(m=30, rtol=1e-10, maxiters=3000, prec="f64")
+    x0, info0, h0 = api.fgmres_solve(S, bd, None, **kw)
+    t0 = api.fgmres_step_times(S, info0["iters"] + 1)
+    assert info0["converged"] == 1 and info0["restarts"] >= 1
+    S.set_timeout(1e6)
+    x1, info1, h1 = api.fgmres_solve(S, bd, None, **kw)
+    assert info1 == info0
+    np.testing.assert_array_equal(h1, h0)
+    np.testing.assert_array_equal(x1.cpu().numpy(), x0.cpu().numpy())
+    S.set_timeout(1e-9)
+    _, info2, _ = api.fgmres_solve(S, bd, None, **kw)
+    assert info2["iters"] == 1 and info2["converged"] == 0
+    _, info2j, _ = api.fgmres_solve_gmres(S, bd, m=10, maxiters=100, prec="f64")
+    assert info2j["iters"] == 1 and info2j["converged"] == 0
+    half = 0.5 * t0[-1]
+    S.set_timeout(half)
+    _, info3, h3 = api.fgmres_solve(S, bd, None, **kw)
+    t3 = api.fgmres_step_times(S, info3["iters"] + 1)
+    print("unlimited", info0["iters"], t0[-1], "half", info3["iters"], t3[-2:], half)
+    assert info3["converged"] == 0 and 1 < info3["iters"] < info0["iters"]
+    assert t3[-2] < half and t3[-1] >= half - 1e-6
+    np.testing.assert_array_equal(h3[:10], h0[:10])
+    S.set_timeout(0.0)
+    _, info4, _ = api.fgmres_solve(S, bd, None, **kw)
+    assert info4 == info0
+    for bad in (-1.0, float("inf"), float("nan")):
+        with pytest.raises(GNPError):
+            S.set_timeout(bad)
