@@ -12,7 +12,13 @@ float32 SpMV and basis, network in bf16 on MFMA (and float32 for
 comparison).  One step = one whole solve from x0 = 0 to rtol 1e-8.
 
 Prints one JSON line with the metric, the roofline figures of the dominant
-kernel and the oracle's host-core baseline.
+kernel and the oracle's host-core baseline.  Untimed extras in its config:
+the same solve with the float32 network, without a preconditioner, with
+Jacobi and with inner-outer GMRES (Sec. 3, "Compared methods"), the paper's
+Iter-AUC / Time-AUC of those four, 32 right-hand sides sequential / served /
+batched, and SpMV bandwidths.  Flags add the serving fleet (--serve), the
+Eq. (3) training sampler (--sampler-compare), the network without the
+scaling of Eq. (6) (--scale-ablation) and evolving systems (--evolve).
 """
 from __future__ import annotations
 
