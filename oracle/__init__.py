@@ -63,6 +63,12 @@ def lib():
         L.or_gnp_nparams.restype = C.c_int64
         L.or_gnp_forward.argtypes = [C.c_int64, I32P, I32P, F64P, C.c_int, C.c_int, C.c_int,
                                      F64P, C.c_int, F64P, F64P, C.c_void_p]
+        L.or_gnp_encoder.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, F64P, C.c_int, F64P,
+                                     F64P]
+        L.or_gnp_layer.argtypes = [C.c_int64, I32P, I32P, F64P, C.c_int, C.c_int, C.c_int, F64P,
+                                   C.c_int, C.c_int, F64P, F64P]
+        L.or_gnp_decoder.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, F64P, C.c_int, F64P,
+                                     F64P, F64P]
         L.or_gnp_loss_grad.argtypes = [C.c_int64, I32P, I32P, F64P, F64P, C.c_int, C.c_int,
                                        C.c_int, F64P, C.c_int, F64P, C.c_void_p, C.c_void_p]
         L.or_gnp_loss_grad.restype = C.c_double
@@ -177,6 +183,39 @@ def gnp_forward(S: System, L, d, h, theta, b, return_acts=False):
     lib().or_gnp_forward(S.n, S.A.rowptr, S.A.colind, S.ahat, L, d, h, _c64(theta), B, b, z,
                          _ptr(acts))
     return (z, acts) if return_acts else z
+
+
+def gnp_encoder(S: System, L, d, h, theta, b):
+    """X_0 = encoder(s(b)) of Sec. 2.3 and Eq. (6); b of shape [n] or [n, B].
+    Returns [n, B, d]."""
+    b = _c64(b)
+    B = 1 if b.ndim == 1 else b.shape[1]
+    E = np.empty((S.n, B, d))
+    lib().or_gnp_encoder(S.n, L, d, h, _c64(theta), B, b, E)
+    return E
+
+
+def gnp_layer(S: System, L, d, h, theta, l, X):
+    """X_{l+1} = ReLU(X_l U_l + (A-hat X_l) W_l), Eq. (5); X of shape
+    [n, B, d] (node-major).  Returns the same shape."""
+    X = _c64(X)
+    assert X.ndim == 3 and X.shape[0] == S.n and X.shape[2] == d and 0 <= l < L
+    Y = np.empty_like(X)
+    lib().or_gnp_layer(S.n, S.A.rowptr, S.A.colind, S.ahat, L, d, h, _c64(theta), int(l),
+                       X.shape[1], X, Y)
+    return Y
+
+
+def gnp_decoder(S: System, L, d, h, theta, b, XL):
+    """z = s^-1(decoder(X_L)) of Sec. 2.3 and Eq. (6), tau = ||b_k|| per
+    right-hand side; XL of shape [n, B, d].  Returns the shape of b."""
+    b = _c64(b)
+    B = 1 if b.ndim == 1 else b.shape[1]
+    XL = _c64(XL)
+    assert XL.shape == (S.n, B, d)
+    z = np.empty_like(b)
+    lib().or_gnp_decoder(S.n, L, d, h, _c64(theta), B, b, XL, z)
+    return z
 
 
 def loss_grad(S: System, L, d, h, theta, b, want_grad=True):

@@ -219,6 +219,92 @@ static double relu(double x) { return x > 0.0 ? x : 0.0; }
 static int g_scaled = 1;
 OR_API void or_set_scaling(int on) { g_scaled = on ? 1 : 0; }
 
+/* s(b) of Eq. (6) per right-hand side: tau = ||b||_2, the input factor
+ * sqrt(n)/tau (0 for b = 0) and the output factor tau/sqrt(n). */
+static void scale_factors(int64_t n, int B, const double *bin, double *tau, double *si, double *so)
+{
+    const double sqn = sqrt((double)n);
+    for (int b = 0; b < B; ++b) {
+        double ss = 0.0;
+        for (int64_t i = 0; i < n; ++i) ss += bin[i * B + b] * bin[i * B + b];
+        double t = sqrt(ss);
+        if (tau) tau[b] = t;
+        si[b] = g_scaled ? (t > 0.0 ? sqn / t : 0.0) : 1.0;
+        so[b] = g_scaled ? t / sqn : 1.0;
+    }
+}
+
+/* MLP encoder of Sec. 2.3 on the scaled input, row by row:
+ * u = si * b, E = ReLU(u W1 + c1) W2 + c2 (pre1 keeps u W1 + c1). */
+static void encoder_rows(int64_t rows, int B, int d, int h, const gnp_view *g, const double *si,
+                         const double *bin, double *u_out, double *pre1, double *E_out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < rows; ++r) {
+        double u = si[r % B] * bin[r];
+        u_out[r] = u;
+        double *p1 = pre1 + r * h;
+        for (int k = 0; k < h; ++k) p1[k] = u * g->W1[k] + g->c1[k];
+        double *E = E_out + r * d;
+        for (int f = 0; f < d; ++f) {
+            double acc = 0.0;
+            for (int k = 0; k < h; ++k) acc += relu(p1[k]) * g->W2[(int64_t)k * d + f];
+            E[f] = acc + g->c2[f];
+        }
+    }
+}
+
+/* One Res-GCONV layer, Eq. (5): T = A-hat X, Y = ReLU(X U + T W), for B
+ * right-hand sides (rows r = i*B + b, d features each). */
+static void layer_rows(int64_t n, const int32_t *rp, const int32_t *ci, const double *ahat, int B,
+                       int d, const double *U, const double *W, const double *X, double *T,
+                       double *Y)
+{
+    const int64_t rows = n * B;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int b = 0; b < B; ++b) {
+            double *Tr = T + (i * B + b) * d;
+            for (int f = 0; f < d; ++f) {
+                double acc = 0.0;
+                for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                    acc += ahat[k] * X[((int64_t)ci[k] * B + b) * d + f];
+                Tr[f] = acc;
+            }
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < rows; ++r) {
+        const double *Xr = X + r * d, *Tr = T + r * d;
+        for (int q = 0; q < d; ++q) {
+            double acc = 0.0;
+            for (int p = 0; p < d; ++p) acc += Xr[p] * U[(int64_t)p * d + q];
+            for (int p = 0; p < d; ++p) acc += Tr[p] * W[(int64_t)p * d + q];
+            Y[r * d + q] = relu(acc);
+        }
+    }
+}
+
+/* MLP decoder and s^-1 of Eq. (6), row by row: o = ReLU(X_L W3 + c3) W4 + c4,
+ * z = so * o (pre3 keeps X_L W3 + c3). */
+static void decoder_rows(int64_t rows, int B, int d, int h, const gnp_view *g, const double *so,
+                         const double *XL, double *pre3, double *o_out, double *z)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < rows; ++r) {
+        double *p3 = pre3 + r * h;
+        for (int k = 0; k < h; ++k) {
+            double acc = 0.0;
+            for (int f = 0; f < d; ++f) acc += XL[r * d + f] * g->W3[(int64_t)f * h + k];
+            p3[k] = acc + g->c3[k];
+        }
+        double acc = 0.0;
+        for (int k = 0; k < h; ++k) acc += relu(p3[k]) * g->W4[k];
+        o_out[r] = acc + g->c4[0];
+        z[r] = so[r % B] * o_out[r];
+    }
+}
+
 /* Forward pass: Eq. (6) scaling, MLP encoder, L Res-GCONV layers (Eq. (5))
  * with A-hat from Eq. (4), MLP decoder, back-scaling. */
 static void gnp_forward_state(int64_t n, const int32_t *rp, const int32_t *ci, const double *ahat,
@@ -227,74 +313,56 @@ static void gnp_forward_state(int64_t n, const int32_t *rp, const int32_t *ci, c
 {
     gnp_view g;
     gnp_unpack(theta, L, d, h, &g);
-    const double sqn = sqrt((double)n);
-    /* s(b) = (sqrt(n)/tau) b with tau = ||b||_2, per right-hand side (Eq. (6)). */
-    for (int b = 0; b < B; ++b) {
-        double ss = 0.0;
-        for (int64_t i = 0; i < n; ++i) ss += bin[i * B + b] * bin[i * B + b];
-        double tau = sqrt(ss);
-        s->tau[b] = tau;
-        s->si[b] = g_scaled ? (tau > 0.0 ? sqn / tau : 0.0) : 1.0;
-        s->so[b] = g_scaled ? tau / sqn : 1.0;
-    }
     const int64_t rows = n * B;
-    /* encoder: E = ReLU(u W1 + c1) W2 + c2 */
-#pragma omp parallel for schedule(static)
-    for (int64_t r = 0; r < rows; ++r) {
-        double u = s->si[r % B] * bin[r];
-        s->u[r] = u;
-        double *p1 = s->pre1 + r * h;
-        for (int k = 0; k < h; ++k) p1[k] = u * g.W1[k] + g.c1[k];
-        double *E = s->X[0] + r * d;
-        for (int f = 0; f < d; ++f) {
-            double acc = 0.0;
-            for (int k = 0; k < h; ++k) acc += relu(p1[k]) * g.W2[(int64_t)k * d + f];
-            E[f] = acc + g.c2[f];
-        }
-    }
-    /* Res-GCONV layers: X_{l+1} = ReLU(X_l U_l + (A-hat X_l) W_l), Eq. (5) */
-    for (int l = 0; l < L; ++l) {
-        const double *X = s->X[l];
-        double *T = s->T[l];
-        double *Y = s->X[l + 1];
-#pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < n; ++i) {
-            for (int b = 0; b < B; ++b) {
-                double *Tr = T + (i * B + b) * d;
-                for (int f = 0; f < d; ++f) {
-                    double acc = 0.0;
-                    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
-                        acc += ahat[k] * X[((int64_t)ci[k] * B + b) * d + f];
-                    Tr[f] = acc;
-                }
-            }
-        }
-#pragma omp parallel for schedule(static)
-        for (int64_t r = 0; r < rows; ++r) {
-            const double *Xr = X + r * d, *Tr = T + r * d;
-            for (int q = 0; q < d; ++q) {
-                double acc = 0.0;
-                for (int p = 0; p < d; ++p) acc += Xr[p] * g.U[l][(int64_t)p * d + q];
-                for (int p = 0; p < d; ++p) acc += Tr[p] * g.W[l][(int64_t)p * d + q];
-                Y[r * d + q] = relu(acc);
-            }
-        }
-    }
-    /* decoder: o = ReLU(X_L W3 + c3) W4 + c4;  z = (tau/sqrt(n)) o */
-    const double *XL = s->X[L];
-#pragma omp parallel for schedule(static)
-    for (int64_t r = 0; r < rows; ++r) {
-        double *p3 = s->pre3 + r * h;
-        for (int k = 0; k < h; ++k) {
-            double acc = 0.0;
-            for (int f = 0; f < d; ++f) acc += XL[r * d + f] * g.W3[(int64_t)f * h + k];
-            p3[k] = acc + g.c3[k];
-        }
-        double acc = 0.0;
-        for (int k = 0; k < h; ++k) acc += relu(p3[k]) * g.W4[k];
-        s->o[r] = acc + g.c4[0];
-        z[r] = s->so[r % B] * s->o[r];
-    }
+    scale_factors(n, B, bin, s->tau, s->si, s->so);
+    encoder_rows(rows, B, d, h, &g, s->si, bin, s->u, s->pre1, s->X[0]);
+    for (int l = 0; l < L; ++l)
+        layer_rows(n, rp, ci, ahat, B, d, g.U[l], g.W[l], s->X[l], s->T[l], s->X[l + 1]);
+    decoder_rows(rows, B, d, h, &g, s->so, s->X[L], s->pre3, s->o, z);
+}
+
+/* The three stages of the forward pass one at a time (the same functions as
+ * or_gnp_forward runs), so that one stage can be evaluated on inputs taken
+ * from elsewhere.  Encoder (with the s(b) of Eq. (6)): E = X_0 for b
+ * ([n][B]); layer l of Eq. (5): Y = X_{l+1} from X = X_l; decoder with
+ * s^-1 of Eq. (6): z from X_L, tau taken from b. */
+OR_API void or_gnp_encoder(int64_t n, int L, int d, int h, const double *theta, int B,
+                           const double *bin, double *E)
+{
+    gnp_view g;
+    gnp_unpack(theta, L, d, h, &g);
+    const int64_t rows = n * B;
+    double *si = (double *)malloc(sizeof(double) * B), *so = (double *)malloc(sizeof(double) * B);
+    double *u = (double *)malloc(sizeof(double) * rows);
+    double *pre1 = (double *)malloc(sizeof(double) * rows * h);
+    scale_factors(n, B, bin, NULL, si, so);
+    encoder_rows(rows, B, d, h, &g, si, bin, u, pre1, E);
+    free(si); free(so); free(u); free(pre1);
+}
+
+OR_API void or_gnp_layer(int64_t n, const int32_t *rp, const int32_t *ci, const double *ahat,
+                         int L, int d, int h, const double *theta, int l, int B, const double *X,
+                         double *Y)
+{
+    gnp_view g;
+    gnp_unpack(theta, L, d, h, &g);
+    double *T = (double *)malloc(sizeof(double) * n * B * d);
+    layer_rows(n, rp, ci, ahat, B, d, g.U[l], g.W[l], X, T, Y);
+    free(T);
+}
+
+OR_API void or_gnp_decoder(int64_t n, int L, int d, int h, const double *theta, int B,
+                           const double *bin, const double *XL, double *z)
+{
+    gnp_view g;
+    gnp_unpack(theta, L, d, h, &g);
+    const int64_t rows = n * B;
+    double *si = (double *)malloc(sizeof(double) * B), *so = (double *)malloc(sizeof(double) * B);
+    double *pre3 = (double *)malloc(sizeof(double) * rows * h);
+    double *o = (double *)malloc(sizeof(double) * rows);
+    scale_factors(n, B, bin, NULL, si, so);
+    decoder_rows(rows, B, d, h, &g, so, XL, pre3, o, z);
+    free(si); free(so); free(pre3); free(o);
 }
 
 /* M(b) for B right-hand sides; acts (optional) receives X_0..X_L, each
