@@ -69,6 +69,7 @@ def lib():
                                    C.c_int, C.c_int, F64P, F64P]
         L.or_gnp_decoder.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_int, F64P, C.c_int, F64P,
                                      F64P, F64P]
+        L.or_init_params.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, F64P]
         L.or_gnp_loss_grad.argtypes = [C.c_int64, I32P, I32P, F64P, F64P, C.c_int, C.c_int,
                                        C.c_int, F64P, C.c_int, F64P, C.c_void_p, C.c_void_p]
         L.or_gnp_loss_grad.restype = C.c_double
@@ -183,6 +184,14 @@ def gnp_forward(S: System, L, d, h, theta, b, return_acts=False):
     lib().or_gnp_forward(S.n, S.A.rowptr, S.A.colind, S.ahat, L, d, h, _c64(theta), B, b, z,
                          _ptr(acts))
     return (z, acts) if return_acts else z
+
+
+def init_params(L, d, h, seed):
+    """The default initial weights: uniform on +-1/sqrt(fan_in) from Philox
+    stream 3 (or_init_params)."""
+    out = np.empty(nparams(L, d, h))
+    lib().or_init_params(L, d, h, int(seed), out)
+    return out
 
 
 def gnp_encoder(S: System, L, d, h, theta, b):

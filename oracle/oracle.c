@@ -578,6 +578,36 @@ OR_API void or_normals_stream(uint64_t seed, uint32_t step, uint32_t stream, int
     for (int64_t e = 0; e < count; ++e) out[e] = or_normal_stream(seed, step, stream, (uint64_t)e);
 }
 
+/* Default initial weights (the paper does not state its initialisation):
+ * every weight and bias uniform on (-1/sqrt(fan_in), 1/sqrt(fan_in)), fan_in
+ * the input width of its linear map (W1, c1: 1; W2, c2: h; U_l, W_l: d;
+ * W3, c3: d; W4, c4: h).  Parameter k takes the 53-bit uniform u in (0, 1)
+ * from the first two output words of Philox4x32-10 at counter
+ * (k_lo, k_hi, 0, 3) and key (seed_lo, seed_hi), and becomes
+ * (2u - 1) / sqrt(fan_in). */
+OR_API void or_init_params(int L, int d, int h, uint64_t seed, double *theta)
+{
+    const int64_t np = gnp_nparams(L, d, h);
+    const int64_t end_enc = (int64_t)h + h + (int64_t)h * d + d;
+    const int64_t end_layers = end_enc + (int64_t)L * 2 * d * d;
+    const int64_t end_w3c3 = end_layers + (int64_t)d * h + h;
+    const double two53 = 9007199254740992.0;
+    for (int64_t k = 0; k < np; ++k) {
+        int fan;
+        if (k < 2 * (int64_t)h) fan = 1;             /* W1, c1 */
+        else if (k < end_enc) fan = h;                /* W2, c2 */
+        else if (k < end_layers) fan = d;             /* U_l, W_l */
+        else if (k < end_w3c3) fan = d;               /* W3, c3 */
+        else fan = h;                                 /* W4, c4 */
+        uint32_t ctr[4] = {(uint32_t)k, (uint32_t)((uint64_t)k >> 32), 0u, 3u};
+        uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+        uint32_t o[4];
+        or_philox4x32_10(ctr, key, o);
+        double u = ((double)(((uint64_t)(o[0] >> 5) << 26) | (o[1] >> 6)) + 0.5) / two53;
+        theta[k] = (2.0 * u - 1.0) / sqrt((double)fan);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Training loop (Sec. 2.2 streaming pairs, Sec. 3 hyperparameters)        */
 /* ------------------------------------------------------------------------ */

@@ -112,3 +112,35 @@ def test_loss_of_exact_inverse_is_zero():
     b = np.random.default_rng(2).random((n, 2)) + 0.5
     loss, g = O.loss_grad(S, 0, 1, 1, th, b)
     assert loss < 1e-15
+
+
+def _fans(L, d, h):
+    """fan_in of every parameter in the packing order: W1, c1 (1), W2, c2
+    (h), L x (U_l, W_l) (d), W3, c3 (d), W4, c4 (h)."""
+    return np.concatenate([np.full(2 * h, 1.0), np.full(h * d + d, float(h)),
+                           np.full(2 * L * d * d, float(d)), np.full(d * h + h, float(d)),
+                           np.full(h + 1, float(h))])
+
+
+@pytest.mark.parametrize("arch", [(4, 16, 32), (8, 32, 64)])
+def test_default_init_params(arch):
+    """The default initialisation (uniform on +-1/sqrt(fan_in), Philox stream
+    3): within each block's bound, mean 0 and variance 1/(3 fan_in) within
+    sampling error, one element rebuilt from the known-answer-pinned Philox
+    words, deterministic in the seed and different across seeds."""
+    from scipy import stats
+    L, d, h = arch
+    th = O.init_params(L, d, h, 7)
+    fan = _fans(L, d, h)
+    assert th.size == fan.size == O.nparams(L, d, h)
+    assert np.all(np.abs(th) < 1 / np.sqrt(fan))
+    w = th * np.sqrt(fan)  # uniform on (-1, 1) if the definition holds
+    assert abs(w.mean()) < 5 * np.sqrt(1 / 3 / w.size)
+    assert abs(w.var() - 1 / 3) < 5 * np.sqrt(4 / 45 / w.size)
+    assert stats.kstest((w + 1) / 2, "uniform").pvalue > 1e-4
+    for k in (0, 2 * h + 5, th.size - 1):
+        o = O.philox([k & 0xFFFFFFFF, k >> 32, 0, 3], [7, 0])
+        u = ((int(o[0] >> 5) << 26 | int(o[1] >> 6)) + 0.5) / 2.0 ** 53
+        assert th[k] == (2 * u - 1) / np.sqrt(fan[k])
+    assert np.array_equal(th, O.init_params(L, d, h, 7))
+    assert not np.any(th == O.init_params(L, d, h, 8))
