@@ -133,12 +133,21 @@ GNP_API gnp_status gnp_spmv(const gnp_system *sys, const void *x_dev, void *y_de
  * the input index first, y = x M):
  *   W1[1 x h] c1[h] W2[h x d] c2[d] | for l < L: U_l[d x d] W_l[d x d] |
  *   W3[d x h] c3[h] W4[h x 1] c4[1]
- * count = 2h + 2hd + d + 2 L d^2 + 2h + 1.  init_params must hold that many
- * values (the library has no random initialiser of its own).
- * Supported (d, h): (16, 32) and (32, 64); 0 <= L <= 64.
- * The model keeps a reference to sys, which must outlive it. */
+ * count = 2h + 2hd + d + 2 L d^2 + 2h + 1.  init_params (host) holds that
+ * many values, or is NULL for the seeded default initialisation (the paper
+ * does not state one): every weight and bias uniform on
+ * (-1/sqrt(fan_in), 1/sqrt(fan_in)), fan_in the input width of its linear
+ * map (W1, c1: 1; W2, c2: h; U_l, W_l: d; W3, c3: d; W4, c4: h), parameter k
+ * = (2u - 1)/sqrt(fan_in) with u the 53-bit uniform in (0, 1) from the first
+ * two output words of Philox4x32-10 at counter (k_lo, k_hi, 0, 3) and key
+ * (seed_lo, seed_hi).  seed is used only when init_params is NULL.
+ * Supported (d, h): (16, 32) and (32, 64); 1 <= L <= 64 (the network has at
+ * least one Res-GCONV layer: the decoder runs fused into the last one).
+ * The model keeps a reference to sys, which must outlive it.
+ * Errors: GNP_EINVAL for a null sys or out, an unsupported (d, h) or L out
+ * of range; GNP_ENUMERIC for a non-finite initial parameter. */
 GNP_API gnp_status gnp_model_create(gnp_system *sys, int L, int d, int h,
-                                    const double *init_params, gnp_model **out);
+                                    const double *init_params, uint64_t seed, gnp_model **out);
 GNP_API void gnp_model_destroy(gnp_model *model);
 GNP_API size_t gnp_model_nparams(const gnp_model *model);
 /* Switch the scale-equivariant wrapping of Eq. (6) off (on = 0) or back on
@@ -417,6 +426,11 @@ typedef struct {
     double solves_per_s;  /* completed / (last completion - first submission) */
     size_t hbm_budget, hbm_used, hbm_peak; /* bytes of solve workspaces held */
     int64_t workspaces_allocated, workspaces_reused, workspaces_evicted;
+    /* requests that completed with a true residual <= their rtol (completed
+     * counts also the ones that stopped at maxiters or a time limit) */
+    int64_t converged;
+    double converged_per_s;                        /* converged / (last converged - first submission) */
+    double conv_latency_p50_s, conv_latency_p99_s; /* over the converged requests */
 } gnp_server_stats;
 
 /* Start a server on the current device.  m: restart length of every solve
@@ -451,6 +465,23 @@ GNP_API gnp_status gnp_server_poll(gnp_server *srv, uint64_t ticket, double *x_h
 /* Block until no request is queued or running, or until timeout_s seconds
  * have passed (GNP_EBUSY). */
 GNP_API gnp_status gnp_server_drain(gnp_server *srv, double timeout_s);
+
+/* Replace the values of registered system `id` while the server runs (the
+ * slowly evolving systems for which the paper keeps training the same
+ * network, Sec. 5 "Discussions and Conclusions"): its queued and newly
+ * submitted requests wait, the requests of it already in slots finish on
+ * the old values, then gnp_system_set_values(sys, val) runs and, with
+ * tune != NULL, gnp_train(model, tune, NULL, loss_hist, best_step) trains
+ * the registered network further on the new matrix; then its requests are
+ * admitted again (the other systems are served throughout).  Blocks the
+ * caller until done.  Training memory is outside the HBM budget.
+ * Errors: GNP_EINVAL for an unknown id, a null val, tune without a
+ * registered network, or what gnp_system_set_values / gnp_train reject (the
+ * system then keeps its old values, or the weights of the failed training);
+ * GNP_EBUSY if an update of the same system is already in progress. */
+GNP_API gnp_status gnp_server_update_system(gnp_server *srv, int id, const double *val,
+                                            const gnp_train_opts *tune, double *loss_hist,
+                                            int *best_step);
 
 GNP_API gnp_status gnp_server_get_stats(gnp_server *srv, gnp_server_stats *out);
 

@@ -48,7 +48,9 @@ class ServerStats(C.Structure):
                 ("solves_per_s", C.c_double), ("hbm_budget", C.c_size_t),
                 ("hbm_used", C.c_size_t), ("hbm_peak", C.c_size_t),
                 ("workspaces_allocated", C.c_int64), ("workspaces_reused", C.c_int64),
-                ("workspaces_evicted", C.c_int64)]
+                ("workspaces_evicted", C.c_int64), ("converged", C.c_int64),
+                ("converged_per_s", C.c_double), ("conv_latency_p50_s", C.c_double),
+                ("conv_latency_p99_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +67,8 @@ SIGNATURES = {
     "gnp_system_n": (C.c_int64, [VP]),
     "gnp_system_nnz": (C.c_int64, [VP]),
     "gnp_spmv": (C.c_int, [VP, VP, VP, C.c_int, VP]),
-    "gnp_model_create": (C.c_int, [VP, C.c_int, C.c_int, C.c_int, VP, C.POINTER(VP)]),
+    "gnp_model_create": (C.c_int, [VP, C.c_int, C.c_int, C.c_int, VP, C.c_uint64,
+                                   C.POINTER(VP)]),
     "gnp_model_destroy": (None, [VP]),
     "gnp_system_set_values": (C.c_int, [VP, VP, VP]),
     "gnp_model_nparams": (C.c_size_t, [VP]),
@@ -100,6 +103,7 @@ SIGNATURES = {
                                     C.POINTER(C.c_uint64)]),
     "gnp_server_poll": (C.c_int, [VP, C.c_uint64, VP, C.POINTER(SolveInfo), F64P]),
     "gnp_server_drain": (C.c_int, [VP, C.c_double]),
+    "gnp_server_update_system": (C.c_int, [VP, C.c_int, VP, VP, VP, C.POINTER(C.c_int)]),
     "gnp_server_get_stats": (C.c_int, [VP, C.POINTER(ServerStats)]),
     "gnp_server_destroy": (None, [VP]),
     "gnp_sampler_create": (C.c_int, [VP, C.c_int, C.c_uint64, C.c_int, VP, C.POINTER(VP)]),

@@ -66,6 +66,12 @@ class System:
     def handle(self):
         return self._h
 
+    def refresh(self):
+        """Re-read gamma after the values changed elsewhere (a server update)."""
+        g0, g1 = C.c_double(), C.c_double()
+        check(_lib.load().gnp_system_gamma(self._h, C.byref(g0), C.byref(g1)))
+        self.gamma_input, self.gamma = g0.value, g1.value
+
     def set_timeout(self, seconds: float):
         """Time limit of every later single solve on this system, 0 = none
         (gnp_system_set_timeout)."""
@@ -127,11 +133,15 @@ class System:
 class Model:
     """Graph neural preconditioner bound to a System (gnp_model_create)."""
 
-    def __init__(self, system: System, L: int, d: int, h: int, params):
+    def __init__(self, system: System, L: int, d: int, h: int, params=None, seed: int = 0):
+        """params: initial weights (float64, the packing of gnp_model_create),
+        or None for the library's seeded default initialisation."""
         lib = _lib.load()
-        th, pth = _host(params, np.float64)
+        pth = None
+        if params is not None:
+            th, pth = _host(params, np.float64)
         hm = C.c_void_p()
-        check(lib.gnp_model_create(system.handle, L, d, h, pth, C.byref(hm)))
+        check(lib.gnp_model_create(system.handle, L, d, h, pth, int(seed), C.byref(hm)))
         self._h = hm
         self.system = system  # keeps the system alive
         self.L, self.d, self.h = L, d, h
@@ -393,6 +403,7 @@ class Server:
                                             int(max_iters), PREC[prec], C.byref(h)))
         self._h = h
         self._n = {}
+        self._sys = {}
         self._keep = []  # systems / models must outlive the server
 
     def register(self, system: System, model: Model | None = None) -> int:
@@ -401,6 +412,7 @@ class Server:
                                               model.handle if model is not None else None,
                                               C.byref(i)))
         self._n[i.value] = system.n
+        self._sys[i.value] = system
         self._keep.append((system, model))
         return i.value
 
@@ -430,6 +442,28 @@ class Server:
             return None
         check(st)
         return x, info.as_dict(), lat.value
+
+    def update_system(self, sid: int, val, tune_steps: int = 0, batch: int = 16,
+                      lr: float = 1e-3, seed: int = 2, prec="f32", betas=(0.9, 0.999),
+                      eps: float = 1e-8):
+        """New values for registered system `sid` while serving
+        (gnp_server_update_system); with tune_steps > 0 its network is
+        trained further on the new matrix.  Returns (loss history, best step)
+        of that training, or None."""
+        v, pv = _host(val, np.float64)
+        if tune_steps > 0:
+            o = TrainOpts(int(tune_steps), int(batch), float(lr), float(betas[0]),
+                          float(betas[1]), float(eps), int(seed), PREC[prec], 0, 0)
+            hist = np.empty(tune_steps)
+            best = C.c_int(-1)
+            check(_lib.load().gnp_server_update_system(self._h, int(sid), pv, C.byref(o),
+                                                       hist.ctypes.data_as(C.c_void_p),
+                                                       C.byref(best)))
+            self._sys[sid].refresh()
+            return hist, best.value
+        check(_lib.load().gnp_server_update_system(self._h, int(sid), pv, None, None, None))
+        self._sys[sid].refresh()
+        return None
 
     def drain(self, timeout_s: float = 600.0):
         check(_lib.load().gnp_server_drain(self._h, float(timeout_s)))

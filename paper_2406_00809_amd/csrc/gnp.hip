@@ -7,6 +7,7 @@
 
 #include "gnp_fwd.hpp"
 #include "model.hpp"
+#include "philox.hpp"
 
 namespace gnp {
 
@@ -296,6 +297,22 @@ static void layer_once_prec(gnp_model *m, int nrhs, gnp_precision prec, hipStrea
     else layer_once<uint16_t, D, H>(m, nrhs, 0, st);
 }
 
+// Default initial weights (the paper leaves the initialisation open): each
+// weight and bias uniform on +-1/sqrt(fan_in) of its linear map, parameter k
+// from the uniform of Philox stream 3 at element k (philox.hpp).
+static void default_init(int L, int d, int h, uint64_t seed, std::vector<double> &th) {
+    const ParamOffsets po = param_offsets(L, d, h);
+    th.resize(po.total);
+    for (int64_t k = 0; k < po.total; ++k) {
+        int fan;
+        if (k < po.W2) fan = 1;           // W1, c1
+        else if (k < po.U0) fan = h;      // W2, c2
+        else if (k < po.W4) fan = d;      // U_l, W_l, W3, c3
+        else fan = h;                     // W4, c4
+        th[k] = (2.0 * uniform_at(seed, 0u, 3u, (uint64_t)k) - 1.0) / sqrt((double)fan);
+    }
+}
+
 static void model_free(gnp_model *m) {
     if (!m) return;
     void *ptrs[] = {m->theta64, m->theta32, m->pk_bf16, m->pk_f32, m->ws.act[0], m->ws.act[1],
@@ -313,14 +330,18 @@ using namespace gnp;
 extern "C" {
 
 gnp_status gnp_model_create(gnp_system *sys, int L, int d, int h, const double *init_params,
-                            gnp_model **out) {
+                            uint64_t seed, gnp_model **out) {
     if (!out) return fail(GNP_EINVAL, "out is null");
     *out = nullptr;
     if (!sys) return fail(GNP_EINVAL, "sys is null");
     if (L < 1 || L > 64) return fail(GNP_EINVAL, "L must be in [1, 64]");
     if (!((d == 16 && h == 32) || (d == 32 && h == 64)))
         return fail(GNP_EINVAL, "supported (d, h): (16, 32), (32, 64)");
-    if (!init_params) return fail(GNP_EINVAL, "init_params is null");
+    std::vector<double> dflt;
+    if (!init_params) {
+        default_init(L, d, h, seed, dflt);
+        init_params = dflt.data();
+    }
     gnp_model *m = new gnp_model();
     m->sys = sys;
     m->L = L;

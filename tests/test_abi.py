@@ -75,6 +75,6 @@ def test_null_arguments_rejected():
     L = _lib.load()
     h = C.c_void_p()
     assert L.gnp_system_create(4, 4, None, None, None, 1, None, C.byref(h)) == 1
-    assert L.gnp_model_create(None, 2, 16, 32, None, C.byref(h)) == 1
+    assert L.gnp_model_create(None, 2, 16, 32, None, 0, C.byref(h)) == 1
     assert L.fgmres_solve(None, None, None, None, 10, 1e-8, 10, 1, None, None, None) == 1
     assert L.gnp_apply(None, None, None, 1, 1, None) == 1

@@ -422,3 +422,23 @@ def test_fgmres_inner_gmres_degenerate_and_errors(api):
     r = O.fgmres(ref, b, 30, 1e-8, 60, ortho=O.CGS2)
     assert _iters_close(info["iters"], r["info"]["iters"])
     np.testing.assert_allclose(hist[:31], r["hist"][:31], rtol=1e-8)
+
+
+@pytest.mark.parametrize("arch", [(4, 16, 32), (8, 32, 64)])
+def test_default_init_equals_oracle(api, arch):
+    """gnp_model_create without initial weights: the seeded default
+    initialisation equals the oracle's bit for bit (both draw Philox stream 3
+    from its published definition)."""
+    L, d, h = arch
+    S = api.System(I.laplace2d(8))
+    for seed in (0, 7, (1 << 40) + 3):
+        M = api.Model(S, L, d, h, None, seed=seed)
+        assert np.array_equal(M.get_params(), O.init_params(L, d, h, seed)), seed
+
+
+def test_model_create_rejects_bad_depth(api):
+    from paper_2406_00809_amd._lib import GNPError
+    S = api.System(I.laplace2d(8))
+    for L in (0, 65, -1):
+        with pytest.raises(GNPError):
+            api.Model(S, L, 16, 32, None, seed=1)
