@@ -13,6 +13,14 @@
 // own, so its result does not depend on what else is in flight.
 // Latency is stamped at submission and when the solution has reached host
 // memory.
+//
+// Registered systems live at stable addresses (one heap object each): the
+// worker keeps pointers to them while requests run, and registration may
+// happen at any time.  A system's values can be replaced while the server
+// runs (gnp_server_update_system, the evolving systems of Sec. 5): its
+// queued requests wait, the running ones finish on the old values, then the
+// values are replaced, the network is optionally trained further, and its
+// requests are admitted again.
 #include <math.h>
 #include <string.h>
 
@@ -20,6 +28,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -58,11 +67,14 @@ struct SrvWorkspace {
 
 enum SlotPhase { PH_IDLE = 0, PH_BEGIN, PH_CYCLE, PH_COPYOUT };
 
+struct SrvSystem;
+
 struct SrvSlot {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
     SrvWorkspace *ws = nullptr;
     SrvRequest *req = nullptr;
+    SrvSystem *sys = nullptr;  // the request's system (stable address)
     int phase = PH_IDLE;
     int it0 = 0;
 };
@@ -71,6 +83,8 @@ struct SrvSystem {
     gnp_system *sys = nullptr;
     gnp_model *model = nullptr;
     size_t ws_bytes = 0;
+    int active = 0;        // slots running a request of this system
+    bool paused = false;   // an update is in progress: admit none of its requests
 };
 
 static gnp_status hip_ok(hipError_t e, const char *what) {
@@ -99,7 +113,7 @@ struct gnp_server {
     std::condition_variable cv_work, cv_done;
     std::thread worker;
     bool stop = false;
-    std::vector<SrvSystem> systems;
+    std::vector<std::unique_ptr<SrvSystem>> systems;
     std::deque<SrvRequest *> queue;
     std::unordered_map<uint64_t, SrvRequest *> requests;
     std::vector<SrvSlot> slots;
@@ -107,18 +121,18 @@ struct gnp_server {
     AdmissionState adm;
     uint64_t next_ticket = 1, stamp = 0;
     // statistics
-    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, converged = 0;
     int64_t ws_alloc = 0, ws_reuse = 0, ws_evict = 0;
     int busy = 0, max_busy = 0;
     size_t peak = 0;
-    std::vector<double> latencies;
-    Clock::time_point t_first, t_last;
+    std::vector<double> latencies, conv_latencies;
+    Clock::time_point t_first, t_last, t_last_conv;
 };
 
 namespace gnp {
 
 static gnp_status ws_alloc(gnp_server *S, int sys_id, SrvWorkspace **out) {
-    const SrvSystem &sy = S->systems[sys_id];
+    const SrvSystem &sy = *S->systems[sys_id];
     SrvWorkspace *w = new SrvWorkspace();
     w->sys_id = sys_id;
     w->bytes = sy.ws_bytes;
@@ -148,9 +162,15 @@ static void finish_locked(gnp_server *S, SrvRequest *r, gnp_status st, const std
     r->done = true;
     r->t_done = Clock::now();
     if (st == GNP_OK) {
+        const double lat = std::chrono::duration<double>(r->t_done - r->t_submit).count();
         ++S->completed;
-        S->latencies.push_back(std::chrono::duration<double>(r->t_done - r->t_submit).count());
+        S->latencies.push_back(lat);
         S->t_last = r->t_done;
+        if (r->info.converged) {
+            ++S->converged;
+            S->conv_latencies.push_back(lat);
+            S->t_last_conv = r->t_done;
+        }
     } else {
         ++S->failed;
     }
@@ -163,6 +183,8 @@ static void release_slot_locked(gnp_server *S, SrvSlot &sl) {
     S->idle.push_back(sl.ws);
     sl.ws = nullptr;
     sl.req = nullptr;
+    if (--sl.sys->active == 0) S->cv_done.notify_all();
+    sl.sys = nullptr;
     sl.phase = PH_IDLE;
     --S->busy;
     S->cv_work.notify_all();
@@ -172,7 +194,7 @@ static void release_slot_locked(gnp_server *S, SrvSlot &sl) {
 static gnp_status start_request(gnp_server *S, SrvSlot &sl) {
     SrvWorkspace *w = sl.ws;
     SrvRequest *r = sl.req;
-    const int64_t n = S->systems[r->sys_id].sys->n;
+    const int64_t n = sl.sys->sys->n;
     memcpy(w->b_pin, r->b.data(), sizeof(double) * n);
     GNP_HIP(hipMemcpyAsync(w->b_dev, w->b_pin, sizeof(double) * n, hipMemcpyHostToDevice, sl.st));
     GNP_HIP(hipMemsetAsync(w->x_dev, 0, sizeof(double) * n, sl.st));
@@ -187,22 +209,32 @@ static gnp_status start_request(gnp_server *S, SrvSlot &sl) {
 static void admit_locked(gnp_server *S) {
     if (S->queue.empty()) return;
     int free_slots = S->max_slots - S->busy;
+    // requests of systems being updated wait in the queue, in order
+    std::vector<size_t> qmap;
     std::vector<AdmitItem> qv;
     qv.reserve(S->queue.size());
-    for (SrvRequest *r : S->queue) qv.push_back({r->sys_id, S->systems[r->sys_id].ws_bytes});
+    for (size_t k = 0; k < S->queue.size(); ++k) {
+        const SrvSystem &sy = *S->systems[S->queue[k]->sys_id];
+        if (sy.paused) continue;
+        qmap.push_back(k);
+        qv.push_back({S->queue[k]->sys_id, sy.ws_bytes});
+    }
+    if (qv.empty()) return;
     std::vector<IdleItem> iv;
     for (SrvWorkspace *w : S->idle) iv.push_back({w->sys_id, w->bytes, w->stamp});
     const std::vector<AdmitDecision> plan = plan_admission(S->adm, free_slots, qv, iv);
     if (plan.empty()) return;
     std::vector<bool> q_taken(S->queue.size(), false), i_taken(S->idle.size(), false);
     for (const AdmitDecision &d : plan) {
-        SrvRequest *r = S->queue[d.qpos];
-        q_taken[d.qpos] = true;
+        const size_t qk = qmap[d.qpos];
+        SrvRequest *r = S->queue[qk];
+        SrvSystem *sy = S->systems[r->sys_id].get();
+        q_taken[qk] = true;
         if (d.kind == AdmitDecision::REJECT) {
             ++S->rejected;
             finish_locked(S, r,
                           GNP_ENOMEM,
-                          "solve workspace of " + std::to_string(S->systems[r->sys_id].ws_bytes) +
+                          "solve workspace of " + std::to_string(sy->ws_bytes) +
                               " bytes exceeds the HBM budget of " +
                               std::to_string(S->adm.budget) + " bytes");
             continue;
@@ -219,7 +251,7 @@ static void admit_locked(gnp_server *S) {
                 ++S->ws_evict;
             }
             if (ws_alloc(S, r->sys_id, &w) != GNP_OK) {
-                S->adm.used -= S->systems[r->sys_id].ws_bytes;
+                S->adm.used -= sy->ws_bytes;
                 finish_locked(S, r, GNP_ENOMEM, gnp_last_error());
                 continue;
             }
@@ -234,6 +266,8 @@ static void admit_locked(gnp_server *S) {
             }
         sl->ws = w;
         sl->req = r;
+        sl->sys = sy;
+        ++sy->active;
         ++S->busy;
         S->max_busy = std::max(S->max_busy, S->busy);
         const gnp_status st = start_request(S, *sl);
@@ -257,7 +291,7 @@ static void admit_locked(gnp_server *S) {
 static gnp_status advance(gnp_server *S, SrvSlot &sl, std::string &msg) {
     SrvWorkspace *w = sl.ws;
     SrvRequest *r = sl.req;
-    const SrvSystem &sy = S->systems[r->sys_id];
+    const SrvSystem &sy = *sl.sys;  // stable: registration never moves it
     const int64_t n = sy.sys->n;
     const Ctl &h = *w->ctx.ctl_host;
     switch (sl.phase) {
@@ -410,13 +444,13 @@ gnp_status gnp_server_create(size_t hbm_budget, int max_slots, int m, int max_it
 gnp_status gnp_server_register(gnp_server *S, gnp_system *sys, gnp_model *model, int *id) {
     if (!S || !sys || !id) return fail(GNP_EINVAL, "null argument");
     if (model && model->sys != sys) return fail(GNP_EINVAL, "model belongs to another system");
-    SrvSystem sy;
-    sy.sys = sys;
-    sy.model = model;
-    sy.ws_bytes = solve_ctx_bytes(sys->n, S->m, S->max_iters, S->prec, model ? model->d : 0) +
-                  2 * sizeof(double) * (size_t)sys->n;
+    auto sy = std::make_unique<SrvSystem>();
+    sy->sys = sys;
+    sy->model = model;
+    sy->ws_bytes = solve_ctx_bytes(sys->n, S->m, S->max_iters, S->prec, model ? model->d : 0) +
+                   2 * sizeof(double) * (size_t)sys->n;
     std::lock_guard<std::mutex> lk(S->mu);
-    S->systems.push_back(sy);
+    S->systems.push_back(std::move(sy));
     *id = (int)S->systems.size() - 1;
     return GNP_OK;
 }
@@ -425,7 +459,7 @@ gnp_status gnp_server_workspace_bytes(gnp_server *S, int id, size_t *bytes) {
     if (!S || !bytes) return fail(GNP_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(S->mu);
     if (id < 0 || id >= (int)S->systems.size()) return fail(GNP_EINVAL, "unknown system id");
-    *bytes = S->systems[id].ws_bytes;
+    *bytes = S->systems[id]->ws_bytes;
     return GNP_OK;
 }
 
@@ -446,7 +480,7 @@ gnp_status gnp_server_submit(gnp_server *S, int id, const double *b_host, double
             delete r;
             return fail(GNP_EBUSY, "server is shutting down");
         }
-        const int64_t n = S->systems[id].sys->n;
+        const int64_t n = S->systems[id]->sys->n;
         r->sys_id = id;
         r->b.assign(b_host, b_host + n);
         r->rtol = rtol;
@@ -493,6 +527,33 @@ gnp_status gnp_server_drain(gnp_server *S, double timeout_s) {
     return ok ? GNP_OK : fail(GNP_EBUSY, "requests still pending at the timeout");
 }
 
+gnp_status gnp_server_update_system(gnp_server *S, int id, const double *val,
+                                    const gnp_train_opts *tune, double *loss_hist,
+                                    int *best_step) {
+    if (!S || !val) return fail(GNP_EINVAL, "null argument");
+    SrvSystem *sy = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (id < 0 || id >= (int)S->systems.size()) return fail(GNP_EINVAL, "unknown system id");
+        sy = S->systems[id].get();
+        if (sy->paused) return fail(GNP_EBUSY, "an update of this system is in progress");
+        if (tune && !sy->model) return fail(GNP_EINVAL, "fine-tuning needs a registered network");
+        sy->paused = true;  // from now on its queued requests wait
+        S->cv_done.wait(lk, [&] { return sy->active == 0; });
+    }
+    // no request of this system is in a slot: its matrix and network are ours
+    gnp_status st = gnp_system_set_values(sy->sys, val, nullptr);
+    if (st == GNP_OK && tune) st = gnp_train(sy->model, tune, nullptr, loss_hist, best_step,
+                                             nullptr);
+    const std::string msg = st == GNP_OK ? std::string() : std::string(gnp_last_error());
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        sy->paused = false;
+    }
+    S->cv_work.notify_all();
+    return st == GNP_OK ? GNP_OK : fail(st, msg);
+}
+
 gnp_status gnp_server_get_stats(gnp_server *S, gnp_server_stats *o) {
     if (!S || !o) return fail(GNP_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(S->mu);
@@ -504,8 +565,13 @@ gnp_status gnp_server_get_stats(gnp_server *S, gnp_server_stats *o) {
     o->queued = (int64_t)S->queue.size();
     o->active = S->busy;
     o->max_active = S->max_busy;
+    o->converged = S->converged;
     o->latency_p50_s = percentile(S->latencies, 50.0);
     o->latency_p99_s = percentile(S->latencies, 99.0);
+    o->conv_latency_p50_s = percentile(S->conv_latencies, 50.0);
+    o->conv_latency_p99_s = percentile(S->conv_latencies, 99.0);
+    const double cspan = std::chrono::duration<double>(S->t_last_conv - S->t_first).count();
+    o->converged_per_s = (S->converged > 0 && cspan > 0.0) ? (double)S->converged / cspan : 0.0;
     double sum = 0.0;
     for (double v : S->latencies) sum += v;
     o->latency_mean_s = S->latencies.empty() ? 0.0 : sum / (double)S->latencies.size();

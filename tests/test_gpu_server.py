@@ -196,3 +196,122 @@ def test_zero_and_nonfinite_rhs(api, fleet):
     with pytest.raises(api.GNPError):
         srv.submit(sid, bn, rtol=-1.0)
     srv.close()
+
+
+def test_converged_counted_apart_from_completed(api, fleet):
+    """Requests that stop at maxiters complete but do not count as converged:
+    throughput and latency percentiles over the converged ones are reported
+    separately."""
+    srv = api.Server(hbm_budget=8 << 30, max_slots=4, m=M_RESTART, max_iters=MAXIT, prec="bf16")
+    _, A, S, M = fleet[2]  # convdiff3d_16 with its network
+    sid = srv.register(S, M)
+    full = [srv.submit(sid, I.rhs_normal(A.n, 70 + i), rtol=RTOL, maxiters=MAXIT)
+            for i in range(3)]
+    short = [srv.submit(sid, I.rhs_normal(A.n, 80 + i), rtol=RTOL, maxiters=3) for i in range(2)]
+    tickets = {t: A.n for t in full + short}
+    res = _collect(srv, tickets)
+    st = srv.stats()
+    print(st, [res[t][1] for t in full])
+    assert all(res[t][1]["converged"] == 1 for t in full)
+    assert all(res[t][1]["converged"] == 0 for t in short)
+    assert st["completed"] == 5 and st["converged"] == 3 and st["failed"] == 0
+    assert 0 < st["converged_per_s"] and 0 < st["solves_per_s"]
+    assert 0 < st["conv_latency_p50_s"] <= st["conv_latency_p99_s"]
+    srv.close()
+
+
+def test_register_while_requests_in_flight(api, fleet):
+    """Systems registered while requests run (the registry grows many times)
+    leave the running requests intact, and requests on the new ids run too."""
+    srv = api.Server(hbm_budget=8 << 30, max_slots=6, m=M_RESTART, max_iters=MAXIT, prec="bf16")
+    ids = [srv.register(S, M) for _, _, S, M in fleet]
+    order, tickets = [], {}
+    for k, (_, A, S, M) in enumerate(fleet):
+        b = I.rhs_normal(A.n, 500 + k)
+        t = srv.submit(ids[k], b, rtol=RTOL, maxiters=MAXIT)
+        tickets[t] = A.n
+        order.append((t, k, b))
+    for rep in range(40):  # re-register the fleet under new ids while they run
+        k = rep % len(fleet)
+        _, A, S, M = fleet[k]
+        nid = srv.register(S, M)
+        if rep % 8 == 0:
+            b = I.rhs_normal(A.n, 600 + rep)
+            t = srv.submit(nid, b, rtol=RTOL, maxiters=MAXIT)
+            tickets[t] = A.n
+            order.append((t, k, b))
+    res = _collect(srv, tickets)
+    for t, k, b in order:
+        name, A, S, M = fleet[k]
+        x, info, _ = res[t]
+        xa, ia = _solve_alone(api, S, M, b)
+        assert info["iters"] == ia["iters"] and np.array_equal(x, xa), name
+    srv.close()
+
+
+def test_update_system_while_serving(api, fleet):
+    """Evolving systems (Sec. 5): new values for a registered system while
+    the server runs, with a short fine-tuning of its network.  Requests
+    submitted after the update are solved on the new matrix: the same result
+    as a single solve with the tuned network, the true residual of the new
+    matrix below rtol, and the oracle's iteration count (FP64, the same tuned
+    weights, the new matrix) within max(1, ceil(10 %)).  Requests queued
+    before it converge on the old or the new values; the other systems are
+    served throughout, unchanged."""
+    import oracle as O
+    import torch
+    A0, A1 = I.convdiff3d(16, 10.0), I.convdiff3d(16, 15.0)
+    assert np.array_equal(A0.colind, A1.colind) and np.array_equal(A0.rowptr, A1.rowptr)
+    S = api.System(A0)
+    M = api.Model(S, 8, 32, 64, I.init_params(8, 32, 64, 44))
+    M.train(100, 8, lr=1e-3, seed=3, prec="f32")
+    srv = api.Server(hbm_budget=8 << 30, max_slots=4, m=M_RESTART, max_iters=MAXIT, prec="bf16")
+    sid = srv.register(S, M)
+    _, Ao, So, Mo = fleet[0]
+    oid = srv.register(So, Mo)
+    before, others, tickets = [], [], {}
+    for i in range(4):
+        b = I.rhs_normal(A0.n, 700 + i)
+        t = srv.submit(sid, b, rtol=RTOL, maxiters=MAXIT)
+        before.append((t, b))
+        tickets[t] = A0.n
+        bo = I.rhs_normal(Ao.n, 710 + i)
+        t = srv.submit(oid, bo, rtol=RTOL, maxiters=MAXIT)
+        others.append((t, bo))
+        tickets[t] = Ao.n
+    hist, best = srv.update_system(sid, A1.val, tune_steps=40, batch=8, lr=1e-4, seed=9)
+    print(f"tuning on the new values: loss {hist[0]:.4f} -> {hist[best]:.4f}")
+    after = []
+    for i in range(4):
+        b = I.rhs_normal(A1.n, 720 + i)
+        t = srv.submit(sid, b, rtol=RTOL, maxiters=MAXIT)
+        after.append((t, b))
+        tickets[t] = A1.n
+    res = _collect(srv, tickets)
+    srv.close()
+    ref1 = O.System(A1)
+    assert S.gamma_input == ref1.gamma_raw
+    th = M.get_params()
+    Ad0 = A0.to_scipy() / O.gamma(A0)
+    Ad1 = ref1.A.to_scipy()
+    for t, b in before:
+        x, info, _ = res[t]
+        assert info["converged"] == 1
+        r0 = np.linalg.norm(b - Ad0 @ x) / np.linalg.norm(b)
+        r1 = np.linalg.norm(b - Ad1 @ x) / np.linalg.norm(b)
+        assert min(r0, r1) <= 1.5 * RTOL, (r0, r1)
+    for t, b in after:
+        x, info, _ = res[t]
+        xa, ia = _solve_alone(api, S, M, b)
+        assert info["iters"] == ia["iters"] and np.array_equal(x, xa)
+        assert info["converged"] == 1
+        assert np.linalg.norm(b - Ad1 @ x) / np.linalg.norm(b) <= 1.5 * RTOL
+        r = O.fgmres(ref1, b, M_RESTART, RTOL, MAXIT, M="gnp", theta=th, arch=(8, 32, 64),
+                     ortho=O.CGS2)
+        it, it_ref = info["iters"], r["info"]["iters"]
+        print(f"after the update: {it} iterations, oracle {it_ref}")
+        assert abs(it - it_ref) <= max(1, int(np.ceil(0.1 * it_ref)))
+    for t, bo in others:
+        x, info, _ = res[t]
+        xa, ia = _solve_alone(api, So, Mo, bo)
+        assert info["iters"] == ia["iters"] and np.array_equal(x, xa)
