@@ -173,6 +173,27 @@ GNP_API gnp_status gnp_params_set_device(gnp_model *model, const double *buf_dev
 GNP_API gnp_status gnp_apply(gnp_model *model, const void *v_dev, void *z_dev, int nrhs,
                              gnp_precision prec, void *hip_stream);
 
+/* gnp_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as gnp_apply, with its workspace (column-norm
+ * partials and counter, tau, two activation blocks) in a fixed array of
+ * GNP_NOALLOC_SCRATCH_BYTES in device memory that the library holds on
+ * every GPU it runs on until the process ends, instead of the model's apply
+ * workspace.  No allocation of any kind; the launches are a fill kernel for
+ * the counter and the apply's kernels, all on hip_stream.
+ * Limit: 256 + 256-rounded (24 nrhs + 8 nrhs * column-norm blocks) + 2 x
+ * 256-rounded (n * nrhs * d * element size: 8, 4 or 2 bytes for F64, F32,
+ * BF16) bytes must fit (the column-norm blocks are at most 1024); the
+ * 64^3 system with d = 32 fits with one right-hand side in float32 and
+ * bfloat16 (80 MiB; float64 needs 128 MiB there).
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one
+ * GPU (other streams, other threads) race and give wrong results; order them
+ * on one stream.  Errors: as gnp_apply, plus GNP_EINVAL when the apply does
+ * not fit in the array. */
+#define GNP_NOALLOC_SCRATCH_BYTES (80u << 20)
+GNP_API gnp_status gnp_apply_noalloc(gnp_model *model, const void *v_dev, void *z_dev, int nrhs,
+                                     gnp_precision prec, void *hip_stream);
+
 /* gnp_apply that also keeps every activation of the network: acts_dev holds
  * (L+1) blocks of n * nrhs * d activations in the precision's storage type
  * (float64, float32, or bfloat16 bit patterns as uint16 for GNP_BF16), node-

@@ -77,6 +77,7 @@ SIGNATURES = {
     "gnp_params_set": (C.c_int, [VP, VP, C.c_size_t]),
     "gnp_params_set_device": (C.c_int, [VP, VP, C.c_size_t, VP]),
     "gnp_apply": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, VP]),
+    "gnp_apply_noalloc": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, VP]),
     "gnp_apply_layers": (C.c_int, [VP, VP, VP, VP, C.c_int, C.c_int, VP]),
     "fgmres_solve": (C.c_int, [VP, VP, VP, VP, C.c_int, C.c_double, C.c_int, C.c_int, VP,
                                C.POINTER(SolveInfo), VP]),

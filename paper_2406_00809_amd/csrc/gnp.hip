@@ -3,6 +3,8 @@
 // forward launch sequence (encoder, L Res-GCONV layers, decoder).
 #include <math.h>
 
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "gnp_fwd.hpp"
@@ -323,11 +325,83 @@ static void model_free(gnp_model *m) {
     delete m;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch memory of gnp_apply_noalloc: a fixed array in device memory (one
+// copy per GPU, held until the process ends) instead of the model's apply
+// workspace, for callers that cannot allocate.  Layout for one call: the
+// column-norm ticket counter, the tau triples, the column-norm partials, the
+// two ping-pong activation blocks, each at a 256-byte boundary.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GNP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::unordered_map<int, unsigned char *> g_scratch_ptr;  // device -> address of its copy
+}  // namespace
+
+// Device address of this GPU's copy of `scratch` (looked up once per device,
+// with that device current; the array's name is not a device address in
+// host code).
+static gnp_status scratch_address(unsigned char **out) {
+    int dev = 0;
+    GNP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        GNP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        it = g_scratch_ptr.emplace(dev, (unsigned char *)p).first;
+    }
+    *out = it->second;
+    return GNP_OK;
+}
+
+__global__ void k_zero_u32(unsigned *p, int count) {
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0u;
+}
+
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 }  // namespace gnp
 
 using namespace gnp;
 
 extern "C" {
+
+gnp_status gnp_apply_noalloc(gnp_model *m, const void *v_dev, void *z_dev, int nrhs,
+                             gnp_precision prec, void *hip_stream) {
+    if (!m || !v_dev || !z_dev) return fail(GNP_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > BLOCK) return fail(GNP_EINVAL, "nrhs must be in [1, 256]");
+    if (!valid_precision(prec)) return fail(GNP_EINVAL, "bad precision");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t n = m->sys->n;
+    const size_t elem = prec == GNP_F64 ? 8 : (prec == GNP_F32 ? 4 : 2);
+    const size_t o_tau = 256;
+    const size_t o_part = o_tau + round256(sizeof(double) * 3 * (size_t)nrhs);
+    const size_t o_act0 =
+        o_part + round256(sizeof(double) * (size_t)colnorm_blocks(n) * (size_t)nrhs);
+    const size_t act = round256((size_t)n * (size_t)nrhs * (size_t)m->d * elem);
+    const size_t need = o_act0 + 2 * act;
+    if (need > (size_t)GNP_NOALLOC_SCRATCH_BYTES)
+        return fail(GNP_EINVAL, "this apply needs " + std::to_string(need) +
+                                    " bytes of scratch; the no-allocation apply holds " +
+                                    std::to_string((size_t)GNP_NOALLOC_SCRATCH_BYTES));
+    unsigned char *base = nullptr;
+    GNP_TRY(scratch_address(&base));
+    unsigned *counter = (unsigned *)base;
+    double *tau = (double *)(base + o_tau), *partial = (double *)(base + o_part);
+    void *act0 = base + o_act0, *act1 = base + o_act0 + act;
+    // the ticket counter must start at zero (an earlier call may have ended
+    // early); a kernel, not a memset, so that the sequence can be captured
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 4);
+    if (prec == GNP_F64)
+        launch_colnorm<double>(m, (const double *)v_dev, nrhs, tau, partial, counter, nullptr,
+                               st);
+    else
+        launch_colnorm<float>(m, (const float *)v_dev, nrhs, tau, partial, counter, nullptr, st);
+    return forward_launch(m, prec, v_dev, z_dev, nrhs, tau, act0, act1, nullptr, st);
+}
+
 
 gnp_status gnp_model_create(gnp_system *sys, int L, int d, int h, const double *init_params,
                             uint64_t seed, gnp_model **out) {
