@@ -523,6 +523,16 @@ GNP_API void gnp_server_destroy(gnp_server *srv);
 GNP_API gnp_status gnp_time_layer(gnp_model *model, int nrhs, gnp_precision prec, int reps,
                                   double *ms_per_launch, void *hip_stream);
 
+/* The same launch timed with cold caches: before every layer launch a fill
+ * kernel writes flush_bytes of flush_dev (device memory of the caller, at
+ * least twice the 256 MB Infinity Cache to evict it and every L2), and the
+ * time of `reps` fills alone is subtracted: *ms_per_launch = ((fill + layer)
+ * x reps - fill x reps) / reps, all between hipEvents on hip_stream;
+ * *ms_flush (optional) = one fill.  Synchronises the stream. */
+GNP_API gnp_status gnp_time_layer_cold(gnp_model *model, int nrhs, gnp_precision prec, int reps,
+                                       void *flush_dev, size_t flush_bytes, double *ms_per_launch,
+                                       double *ms_flush, void *hip_stream);
+
 /* Mean duration (ms) of one gnp_spmv launch (y = A x), measured the same way. */
 GNP_API gnp_status gnp_time_spmv(const gnp_system *sys, const void *x_dev, void *y_dev,
                                  gnp_precision prec, int reps, double *ms_per_launch,

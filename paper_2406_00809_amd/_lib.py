@@ -95,6 +95,8 @@ SIGNATURES = {
     "gnp_forward_save": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, VP]),
     "gnp_backward": (C.c_int, [VP, VP, VP, VP]),
     "gnp_time_layer": (C.c_int, [VP, C.c_int, C.c_int, C.c_int, F64P, VP]),
+    "gnp_time_layer_cold": (C.c_int, [VP, C.c_int, C.c_int, C.c_int, VP, C.c_size_t, F64P,
+                                      F64P, VP]),
     "gnp_time_spmv": (C.c_int, [VP, VP, VP, C.c_int, C.c_int, F64P, VP]),
     "gnp_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.POINTER(VP)]),

@@ -217,6 +217,18 @@ class Model:
                                          _stream(stream)))
         return ms.value
 
+    def time_layer_cold(self, flush: torch.Tensor, nrhs=1, prec="bf16", reps=50, stream=None):
+        """(ms per layer launch, ms per flush) with the caches evicted before
+        every launch by writing the float32 tensor `flush` (gnp_time_layer_cold)."""
+        ms, mf = C.c_double(), C.c_double()
+        if flush.dtype != torch.float32 or not flush.is_cuda or not flush.is_contiguous():
+            raise TypeError("flush must be a contiguous float32 device tensor")
+        check(_lib.load().gnp_time_layer_cold(self._h, int(nrhs), PREC[prec], int(reps),
+                                              C.c_void_p(flush.data_ptr()),
+                                              flush.numel() * 4, C.byref(ms), C.byref(mf),
+                                              _stream(stream)))
+        return ms.value, mf.value
+
     def loss_grad(self, b: torch.Tensor, prec="f64", stream=None):
         """gnp_loss_grad on b ([n] or [n, nrhs], float64 device)."""
         nrhs = 1 if b.dim() == 1 else b.shape[1]

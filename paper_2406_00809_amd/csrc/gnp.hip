@@ -46,6 +46,13 @@ __global__ void k_copy_f32(const double *__restrict__ a, float *__restrict__ b, 
     if (p < n) b[p] = (float)a[p];
 }
 
+// Stores v into every element of p[0, count) (evicts caches for cold timing).
+__global__ void k_fill_f32(float *__restrict__ p, int64_t count, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 gnp_status model_repack(gnp_model *m, hipStream_t st) {
     const int L = m->L, d = m->d, h = m->h;
     hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(m->np, BLOCK)), dim3(BLOCK), 0, st, m->theta64,
@@ -514,6 +521,51 @@ gnp_status gnp_time_layer(gnp_model *m, int nrhs, gnp_precision prec, int reps,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *ms_per_launch = (double)ms / reps;
+    return GNP_OK;
+}
+
+gnp_status gnp_time_layer_cold(gnp_model *m, int nrhs, gnp_precision prec, int reps,
+                               void *flush_dev, size_t flush_bytes, double *ms_per_launch,
+                               double *ms_flush, void *hip_stream) {
+    if (!m || !flush_dev || !ms_per_launch) return fail(GNP_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > BLOCK || reps < 1) return fail(GNP_EINVAL, "bad nrhs or reps");
+    if (flush_bytes < 4) return fail(GNP_EINVAL, "flush_bytes must be >= 4");
+    if (!valid_precision(prec)) return fail(GNP_EINVAL, "bad precision");
+    hipStream_t st = (hipStream_t)hip_stream;
+    GNP_TRY(model_workspace(m, nrhs));
+    const int64_t nf = (int64_t)(flush_bytes / 4);
+    auto layer = [&]() {
+        if (m->d == 16) layer_once_prec<16, 32>(m, nrhs, prec, st);
+        else layer_once_prec<32, 64>(m, nrhs, prec, st);
+    };
+    auto flush = [&](int r) {
+        hipLaunchKernelGGL(k_fill_f32, dim3(2048), dim3(BLOCK), 0, st, (float *)flush_dev, nf,
+                           (float)r);
+    };
+    hipEvent_t e0, e1, e2;
+    GNP_HIP(hipEventCreate(&e0));
+    GNP_HIP(hipEventCreate(&e1));
+    GNP_HIP(hipEventCreate(&e2));
+    flush(0);
+    layer();  // instruction cache and workspace
+    GNP_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) {
+        flush(r + 1);
+        layer();
+    }
+    GNP_HIP(hipEventRecord(e1, st));
+    for (int r = 0; r < reps; ++r) flush(reps + r + 1);
+    GNP_HIP(hipEventRecord(e2, st));
+    GNP_HIP(hipEventSynchronize(e2));
+    float both = 0.f, fl = 0.f;
+    GNP_HIP(hipEventElapsedTime(&both, e0, e1));
+    GNP_HIP(hipEventElapsedTime(&fl, e1, e2));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    *ms_per_launch = (double)(both - fl) / reps;
+    if (ms_flush) *ms_flush = (double)fl / reps;
+    GNP_HIP(hipGetLastError());
     return GNP_OK;
 }
 
