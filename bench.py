@@ -305,6 +305,9 @@ def main():
     ap.add_argument("--inner-outer-only", action="store_true",
                     help="only time inner-outer GMRES on the benchmark system (outer FGMRES(10), "
                          "inner GMRES(10) to 1e-6, FP32), for a kernel profile of that method")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the cold-cache layer timing (profiled runs: its 50 cold launches "
+                         "would enter the layer kernel's mean)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the float32-network comparison solves")
     args = ap.parse_args()
@@ -678,9 +681,11 @@ def main():
     # before every launch evicts the Infinity Cache and every L2, so the
     # layer's bytes come from HBM.
     lay_ms = M.time_layer(nrhs=1, prec=args.prec, reps=200)
-    flush = torch.empty(128 << 20, dtype=torch.float32, device=dev)
-    lay_cold_ms, fill_ms = M.time_layer_cold(flush, nrhs=1, prec=args.prec, reps=50)
-    del flush
+    lay_cold_ms = float("nan")
+    if not args.no_cold:
+        flush = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+        lay_cold_ms, _ = M.time_layer_cold(flush, nrhs=1, prec=args.prec, reps=50)
+        del flush
     s_act = {"bf16": 2, "f32": 4, "f64": 8}[args.prec]
     # algorithmic bytes of one Res-GCONV layer: colind and A-hat values
     # (counted at 4 bytes each), rowptr, X read once, Y written once

@@ -239,7 +239,8 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     const void *__restrict__ w2, G *__restrict__ E, const int *__restrict__ skip,
     BasisNext bn, int64_t n) {
     static_assert(sizeof(G) <= 4, "MFMA encoder");
-    if (skip && *skip) return;
+    // the skip flag is tested after the weights are loaded (overlapped)
+    const int skipped = skip ? *skip : 0;
     const double *hdiv = bn.hdiv;
     const bool corr = hdiv && bn.V;  // the second Gram-Schmidt correction here
     const int lane = threadIdx.x % WAVE;
@@ -277,6 +278,7 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     const int64_t ntiles = (rows + 15) / 16, nw = (int64_t)gridDim.x * (BLOCK / WAVE);
     int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
     IN vn = v[t * 16 + lane % 16 < rows ? t * 16 + lane % 16 : rows - 1];
+    if (skipped) return;
     // with the correction: rows t*16 + 8 rho + lane/8 (rho = 0, 1), lane
     // q = lane % 8 holding basis columns 4q..4q+3 of its row and the row's w;
     // columns past j are masked below (they may hold an older cycle)
@@ -754,7 +756,9 @@ __device__ __forceinline__ void layer_tiles_bf16(
     const void *__restrict__ wcat, const void *__restrict__ w3, const float *__restrict__ vec,
     int64_t oc3, int64_t oW4, int64_t oc4, const double *__restrict__ tau, ZT *__restrict__ z,
     const int *__restrict__ skip) {
-    if (skip && *skip) return;
+    // the skip flag (end of a solver cycle) is tested after the weights are
+    // staged, so that its load overlaps theirs
+    const int skipped = skip ? *skip : 0;
     using G = uint16_t;
     constexpr int LD = 2 * D + lds_pad<G>();
     // SHORT (every row has at most 7 entries): 7 neighbour slots per batch
@@ -787,6 +791,7 @@ __device__ __forceinline__ void layer_tiles_bf16(
         }
         __syncthreads();
     }
+    if (skipped) return;
     const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv);
     const int64_t ntiles = walk.end, nw = walk.stride;
     const uint32_t rowbytes = (uint32_t)B * (uint32_t)(D * sizeof(G));

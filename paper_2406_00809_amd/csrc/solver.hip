@@ -370,8 +370,10 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                                                const KT *__restrict__ vcur,
                                                KT *__restrict__ vout) {
     ctl += blockIdx.y;
-    if (ctl->cycle_done) return;
-    const double hdiv = MODE == 3 ? ctl->hnext : 1.0;
+    // the end-of-cycle flag is tested only after the first round of loads
+    // has been issued (the loads are in bounds either way), so its latency
+    // overlaps theirs
+    const int done = ctl->cycle_done;
     V += blockIdx.y * bt.basis;
     w += blockIdx.y * bt.vec;
     if (MODE == 0) vcur += blockIdx.y;
@@ -394,6 +396,8 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
     constexpr int RU = RU0 < 2 ? 2 : RU0;
     // the lane owning column j (MODE 0 stores it)
     const bool owner_j = q == ((j >> 2) & 7);
+    double hdiv = 1.0;
+    bool first = true;
     for (int64_t ib = i0 + g; ib < i1; ib += (int64_t)RPP * RU) {
         KT v[RU][NA];
         KT wold[RU], vj[RU];
@@ -413,6 +417,11 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
             }
             wold[ru] = w[ic];
             if (MODE == 0) vj[ru] = vcur[ic * bt.vstep];
+        }
+        if (first) {
+            if (done) return;
+            if (MODE == 3) hdiv = ctl->hnext;
+            first = false;
         }
 #pragma unroll
         for (int ru = 0; ru < RU; ++ru) {
@@ -452,6 +461,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
             if (MODE <= 1 && q == 0) nrm += wi * wi;
         }
     }
+    if (done) return;                 // rows of no round (the tail block)
     if constexpr (MODE >= 2) return;  // no sums
     __shared__ double sh[BLOCK / WAVE][8 * NA + 1];
     const int lane = t % WAVE, wv = t / WAVE;
@@ -486,46 +496,36 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
     }
 }
 
-// first dots finalize: h1[0..j] and ||A z_j|| from the norm slot
+// First dots finalize, one block per column: block k <= j sums h1[k] = (V^T w)_k,
+// block j + 1 the squared norm slot (||A z_j||), each over the pass's block
+// partials in one fixed order (sum_partials), so the bits do not depend on
+// scheduling.  Launched with j + 2 blocks per right-hand side.
 __global__ __launch_bounds__(BLOCK) void k_fin_dots(int nblk, int j, const double *partial,
                                                     int pstride, double *hout, Ctl *ctl, Bat bt) {
     ctl += blockIdx.y;
     if (ctl->cycle_done) return;
+    const int k = blockIdx.x;
     partial += blockIdx.y * bt.part;
     hout += blockIdx.y * bt.small;
-    __shared__ double res[MAXCOL + 1];
-    reduce_columns(nblk, j + 1, partial, pstride, res, pstride - 1);
-    for (int k = threadIdx.x; k <= j; k += BLOCK) hout[k] = res[k];
-    if (threadIdx.x == 0) ctl->wnorm0 = sqrt(res[j + 1]);
+    __shared__ double sh[BLOCK / WAVE];
+    const double s = sum_partials(nblk, partial + (k <= j ? k : pstride - 1), pstride, sh);
+    if (threadIdx.x == 0) {
+        if (k <= j) hout[k] = s;
+        else ctl->wnorm0 = sqrt(s);
+    }
 }
 
-// End of an Arnoldi step, after the second pass: h2[0..j] = V^T w1 and
-// ||w1||^2 (w1: w after the first projection) from that pass's partials;
+// End of an Arnoldi step: h2[0..j] = V^T w1 and h2[j + 1] = ||w1||^2 (w1: w
+// after the first projection);
 // h_{j+1,j} = ||w1 - V h2|| = sqrt(||w1||^2 - ||h2||^2), exact for
 // orthonormal V and h2 = V^T w1 (h2 is a small correction, so nothing
 // cancels; a negative difference from rounding counts as 0, a breakdown);
 // column j of H-bar = h1 + h2, Givens rotation, residual estimate,
 // end-of-cycle decision.  The third pass then only updates w.  Inputs are
 // staged in LDS by all threads, the sequential rotation runs in one thread.
-__global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const double *partial,
-                                                      int pstride, const double *h1, double *h2,
-                                                      Ctl *ctl, double *H, double *H0,
-                                                      double *cs, double *sn, double *g,
-                                                      double *hist, Bat bt, uint64_t *tstamp) {
-    {
-        const int bi = blockIdx.y;
-        ctl += bi;
-        partial += bi * bt.part;
-        h1 += bi * bt.small;
-        h2 += bi * bt.small;
-        H += bi * bt.hess;
-        H0 += bi * bt.hess;
-        cs += bi * bt.small;
-        sn += bi * bt.small;
-        g += bi * bt.small;
-        if (hist) hist += bi * bt.hist;
-    }
-    if (ctl->cycle_done) return;
+__device__ void givens_step(int j, const double *h1, const double *h2, Ctl *ctl, double *H,
+                            double *H0, double *cs, double *sn, double *g, double *hist,
+                            uint64_t *tstamp) {
     __shared__ double res[MAXCOL + 1];
     __shared__ double col[MAXCOL], scs[MAXCOL], ssn[MAXCOL];
     __shared__ double gj_s;
@@ -535,9 +535,9 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const dou
         ssn[i] = sn[i];
     }
     if (threadIdx.x == 0) gj_s = g[j];
-    reduce_columns(nblk, j + 1, partial, pstride, res, pstride - 1);  // ends with a barrier
+    for (int i = threadIdx.x; i <= j + 1; i += BLOCK) res[i] = h2[i];
+    __syncthreads();
     for (int i = threadIdx.x; i <= j; i += BLOCK) {
-        h2[i] = res[i];
         col[i] = h1[i] + res[i];
         H0[(int64_t)i * m + j] = col[i];
     }
@@ -594,6 +594,37 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int nblk, int j, const dou
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= j + 1; i += BLOCK) H[(int64_t)i * m + j] = col[i];
+}
+
+// The second pass's sums, one block per column, the same way as k_fin_dots:
+// h2[k] = (V^T w1)_k for k <= j and h2[j + 1] = ||w1||^2, for k_fin_givens.
+// Launched with j + 2 blocks per right-hand side.  (Completing the step in
+// the last block to finish, behind a ticket, was measured slower: the
+// fences that make the other blocks' sums visible cost more than a launch.)
+__global__ __launch_bounds__(BLOCK) void k_fin_sums2(int nblk, int j, const double *partial,
+                                                     int pstride, double *h2, const Ctl *ctl,
+                                                     Bat bt) {
+    ctl += blockIdx.y;
+    const int k = blockIdx.x;
+    partial += blockIdx.y * bt.part;
+    h2 += blockIdx.y * bt.small;
+    __shared__ double sh[BLOCK / WAVE];
+    if (ctl->cycle_done) return;
+    const double s = sum_partials(nblk, partial + (k <= j ? k : pstride - 1), pstride, sh);
+    if (threadIdx.x == 0) h2[k] = s;
+}
+
+// One block: the rest of the Arnoldi step (givens_step) from h1 and h2.
+__global__ __launch_bounds__(BLOCK) void k_fin_givens(int j, const double *h1, const double *h2,
+                                                      Ctl *ctl, double *H, double *H0,
+                                                      double *cs, double *sn, double *g,
+                                                      double *hist, Bat bt, uint64_t *tstamp) {
+    const int bi = blockIdx.y;
+    ctl += bi;
+    if (ctl->cycle_done) return;
+    givens_step(j, h1 + bi * bt.small, h2 + bi * bt.small, ctl, H + bi * bt.hess,
+                H0 + bi * bt.hess, cs + bi * bt.small, sn + bi * bt.small, g + bi * bt.small,
+                hist ? hist + bi * bt.hist : nullptr, tstamp);
 }
 
 // y = R^{-1} g on the leading columns with nonzero pivots: the triangle and g
@@ -847,14 +878,17 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
                            Bat{}, (const KT *)vcur, (KT *)nullptr);
-        hipLaunchKernelGGL(k_fin_dots, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
+        hipLaunchKernelGGL(k_fin_dots, dim3(j + 2), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, Bat{});
         hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)c->h1, c->partial, pstride, (const Ctl *)c->ctl,
                            Bat{}, (const KT *)nullptr, (KT *)nullptr);
-        hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, gcgs, j,
-                           (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
-                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, Bat{}, c->tstamp);
+        hipLaunchKernelGGL(k_fin_sums2, dim3(j + 2), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, c->h2, (const Ctl *)c->ctl,
+                           Bat{});
+        hipLaunchKernelGGL(k_fin_givens, dim3(1), dim3(BLOCK), 0, st, j, (const double *)c->h1,
+                           (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
+                           c->hist, Bat{}, c->tstamp);
         if (!v_in_encoder)  // third pass and v_{j+1} = w / h_{j+1,j} in one kernel
             hipLaunchKernelGGL((k_cgs<KT, MP, 3>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j,
                                w, (const double *)c->h2, c->partial, pstride,
@@ -1099,15 +1133,16 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
         hipLaunchKernelGGL((k_cgs<float, MP, 0>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
                            bt, (const float *)c->vpk, (float *)nullptr);
-        hipLaunchKernelGGL(k_fin_dots, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
+        hipLaunchKernelGGL(k_fin_dots, dim3(j + 2, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, bt);
         hipLaunchKernelGGL((k_cgs<float, MP, 1>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)c->h1, c->partial, pstride, (const Ctl *)c->ctl,
                            bt, (const float *)nullptr, (float *)nullptr);
-        hipLaunchKernelGGL(k_fin_givens, dim3(1, nb), dim3(BLOCK), 0, st, gcgs, j,
-                           (const double *)c->partial, pstride, (const double *)c->h1, c->h2,
-                           c->ctl, c->H, c->H0, c->cs, c->sn, c->g, c->hist, bt,
-                           (uint64_t *)nullptr);
+        hipLaunchKernelGGL(k_fin_sums2, dim3(j + 2, nb), dim3(BLOCK), 0, st, gcgs, j,
+                           (const double *)c->partial, pstride, c->h2, (const Ctl *)c->ctl, bt);
+        hipLaunchKernelGGL(k_fin_givens, dim3(1, nb), dim3(BLOCK), 0, st, j, (const double *)c->h1,
+                           (const double *)c->h2, c->ctl, c->H, c->H0, c->cs, c->sn, c->g,
+                           c->hist, bt, (uint64_t *)nullptr);
         hipLaunchKernelGGL((k_cgs<float, MP, 2>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)c->h2, c->partial, pstride, (const Ctl *)c->ctl,
                            bt, (const float *)nullptr, (float *)nullptr);
