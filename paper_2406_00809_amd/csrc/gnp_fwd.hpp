@@ -1022,6 +1022,269 @@ __device__ __forceinline__ void layer_tiles_bf16(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Float32 Res-GCONV layer (Eq. (5)), pipelined like layer_tiles_bf16: the
+// same tile walk, CSR slice staging and one memory round trip per tile, with
+// float32 activations (32 bytes per lane and row for d = 32, two buffer
+// loads), A-hat in float32, FP32 FMA gathers and the [X | T] [U; W] product
+// on v_mfma_f32_16x16x4f32 with the weight fragments staged in LDS.  With
+// DEC the decoder follows on the tile (W3 on MFMA as well).  Per row the
+// arithmetic is that of the one-right-hand-side and the several-right-hand-
+// side variants alike (neighbours in CSR order, the same MFMA sequence).
+// ---------------------------------------------------------------------------
+template <int BYTES>
+__device__ __forceinline__ Chunk<BYTES> buffer_chunk_f(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (BYTES <= 16) {
+        return buffer_chunk<BYTES>(r, off);
+    } else {
+        static_assert(BYTES == 32, "chunk of up to 32 bytes");
+        // off is either in range or at least BUF_OOB (out of range for both halves)
+        const uint32_t off2 = off >= BUF_OOB ? off : off + 16u;
+        Chunk<32> c;
+        const Chunk<16> a = buffer_chunk<16>(r, off), b = buffer_chunk<16>(r, off2);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            c.w[i] = a.w[i];
+            c.w[4 + i] = b.w[i];
+        }
+        return c;
+    }
+}
+
+template <int D, int H, bool DEC, bool B1, bool SHORT, typename ZT>
+__device__ __forceinline__ void layer_tiles_f32p(
+    int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const float *__restrict__ ahat, const float *__restrict__ X, float *__restrict__ Y,
+    const void *__restrict__ wcat, const void *__restrict__ w3, const float *__restrict__ vec,
+    int64_t oc3, int64_t oW4, int64_t oc4, const double *__restrict__ tau, ZT *__restrict__ z,
+    const int *__restrict__ skip) {
+    const int skipped = skip ? *skip : 0;
+    using G = float;
+    constexpr int LD = 2 * D + lds_pad<G>();
+    constexpr int CAP = SHORT ? 128 : 256, NC = CAP / WAVE;
+    constexpr int KS = 2 * D / 4, NT = D / 16;    // MFMA k-steps and n-tiles
+    constexpr int CB = (D / 4) * (int)sizeof(G);  // bytes per lane per row
+    constexpr int NB = SHORT ? 7 : 8;             // neighbour loads per batch
+    constexpr int NW3 = DEC ? (D / 4) * (H / 16) * WAVE : 1;  // W3 fragments
+    __shared__ __attribute__((aligned(16))) G As[BLOCK / WAVE][16][LD];
+    __shared__ uint32_t sCo[BLOCK / WAVE][CAP];  // byte offset of row (column, rhs 0) in X
+    __shared__ float sVa[BLOCK / WAVE][CAP];
+    __shared__ __attribute__((aligned(16))) float sW[KS * NT * WAVE];
+    __shared__ __attribute__((aligned(16))) float sW3[NW3];
+    __shared__ __attribute__((aligned(16))) float sC3[DEC ? H : 4], sW4[DEC ? H : 4];
+    const int lane = threadIdx.x % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    {
+        const float4 *src = reinterpret_cast<const float4 *>(wcat);
+        for (int e = threadIdx.x; e < KS * NT * WAVE / 4; e += BLOCK)
+            reinterpret_cast<float4 *>(sW)[e] = src[e];
+        if constexpr (DEC) {
+            const float4 *src3 = reinterpret_cast<const float4 *>(w3);
+            for (int e = threadIdx.x; e < NW3 / 4; e += BLOCK)
+                reinterpret_cast<float4 *>(sW3)[e] = src3[e];
+            for (int e = threadIdx.x; e < H; e += BLOCK) {
+                sC3[e] = vec[oc3 + e];
+                sW4[e] = vec[oW4 + e];
+            }
+        }
+        __syncthreads();
+    }
+    if (skipped) return;
+    const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv);
+    const int64_t ntiles = walk.end, nw = walk.stride;
+    const uint32_t rowbytes = (uint32_t)B * (uint32_t)(D * sizeof(G));
+    const int rshift = (rowbytes & (rowbytes - 1)) == 0 ? __builtin_ctz(rowbytes) : -1;
+    // X holds rows * D features (< 2^32 bytes, checked by the launcher)
+    const __amdgpu_buffer_rsrc_t xr = buffer_rsrc(X, (uint32_t)rows * (uint32_t)(D * sizeof(G)));
+
+    auto node_range = [&](int64_t t, uint32_t &ifirst, int &nn) {
+        const uint32_t tt = (uint32_t)(t < ntiles ? t : ntiles - 1);
+        const uint32_t r0 = tt * 16u;
+        const uint32_t rlast = r0 + 15u < (uint32_t)rows ? r0 + 15u : (uint32_t)rows - 1u;
+        ifirst = B1 ? r0 : r0 / (uint32_t)B;
+        nn = (int)((B1 ? rlast : rlast / (uint32_t)B) - ifirst) + 1;
+    };
+    auto fetch_rp = [&](int64_t t) -> int32_t {
+        uint32_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        return rp[ifirst + (uint32_t)(lane <= nn ? lane : nn)];
+    };
+    auto slice_range = [&](int64_t t, int32_t rpv, int32_t &kbeg, int32_t &cnt) {
+        uint32_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        kbeg = __builtin_amdgcn_readfirstlane(rpv);
+        cnt = __builtin_amdgcn_readlane(rpv, nn) - kbeg;
+    };
+    auto fetch_csr = [&](int32_t kbeg, int32_t cnt, int32_t (&cv)[NC], float (&av)[NC]) {
+        const int32_t base = cnt > 0 ? kbeg : (kbeg > 0 ? kbeg - 1 : 0);
+        const int32_t lim = cnt > 0 ? cnt - 1 : 0;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            const int idx = lane + WAVE * u;
+            const uint32_t k = (uint32_t)(base + (idx < lim ? idx : lim));
+            cv[u] = ci[k];
+            av[u] = ahat[k];
+        }
+    };
+    auto commit = [&](int32_t cnt, const int32_t (&cv)[NC], const float (&av)[NC]) {
+        if (cnt <= CAP) {
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                const int idx = lane + WAVE * u;
+                sCo[wv][idx] = rshift >= 0 ? (uint32_t)cv[u] << rshift : (uint32_t)cv[u] * rowbytes;
+                sVa[wv][idx] = av[u];
+            }
+        }
+    };
+
+    int64_t t = walk.t;
+    int32_t rp0 = fetch_rp(t);
+    int32_t kb0, cnt0;
+    slice_range(t, rp0, kb0, cnt0);
+    int32_t rp1 = fetch_rp(t + nw);
+    {
+        int32_t cv[NC];
+        float av[NC];
+        fetch_csr(kb0, cnt0, cv, av);
+        commit(cnt0, cv, av);
+    }
+    int32_t kb1, cnt1;
+    slice_range(t + nw, rp1, kb1, cnt1);
+    wave_lds_sync();
+    for (; t < ntiles; t += nw) {
+        const int64_t r0 = t * 16;
+        uint32_t ifirst;
+        int nn;
+        node_range(t, ifirst, nn);
+        const int32_t kbeg = kb0;
+        const bool staged = cnt0 <= CAP;
+        int32_t cv1[NC];
+        float av1[NC];
+        fetch_csr(kb1, cnt1, cv1, av1);
+        const int32_t rp2 = fetch_rp(t + 2 * nw);
+        // ---- gather T = A-hat X and the row's own X into the LDS tile
+        {
+            const int rl = lane / 4, q = lane % 4;
+            const int64_t r = r0 + rl;
+            const bool valid = r < rows;
+            const uint32_t rr = (uint32_t)(valid ? r : r0);
+            const uint32_t i = B1 ? rr : rr / (uint32_t)B;
+            const uint32_t b = rr - i * (uint32_t)B;
+            const int li = (int)(i - ifirst);
+            const int32_t ks = valid ? __shfl(rp0, li, WAVE) - kbeg : 0;
+            const int32_t ke = valid ? __shfl(rp0, li + 1, WAVE) - kbeg : 0;
+            const uint32_t lane_off = (b * D + (uint32_t)(q * (D / 4))) * (uint32_t)sizeof(G);
+            const uint32_t own_off = (rr * D + (uint32_t)(q * (D / 4))) * (uint32_t)sizeof(G);
+            const Chunk<CB> own = buffer_chunk_f<CB>(xr, valid ? own_off : BUF_OOB);
+            float ta[D / 4];
+#pragma unroll
+            for (int e = 0; e < D / 4; ++e) ta[e] = 0.f;
+            auto acc_chunk = [&](const Chunk<CB> &raw, float a) {
+#pragma unroll
+                for (int e = 0; e < CB / 4; ++e)
+                    ta[e] = __builtin_fmaf(a, __builtin_bit_cast(float, raw.w[e]), ta[e]);
+            };
+            if (staged) {
+                for (int32_t k0 = ks; k0 < ke; k0 += NB) {
+                    Chunk<CB> raw[NB];
+                    float wgt[NB];
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const int32_t kk = k0 + u < CAP ? k0 + u : CAP - 1;
+                        wgt[u] = sVa[wv][kk];
+                        const uint32_t oob = k0 + u < ke ? 0u : BUF_OOB;
+                        raw[u] = buffer_chunk_f<CB>(xr, (sCo[wv][kk] + lane_off) | oob);
+                    }
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) acc_chunk(raw[u], wgt[u]);
+                }
+            } else {
+                for (int32_t k = kbeg + ks; k < kbeg + ke; ++k) {
+                    const uint32_t c = (uint32_t)ci[k];
+                    acc_chunk(buffer_chunk_f<CB>(xr, c * rowbytes + lane_off), ahat[k]);
+                }
+            }
+            *reinterpret_cast<Chunk<CB> *>(&As[wv][rl][q * (D / 4)]) = own;
+            store_feats<G, D / 4>(&As[wv][rl][D + q * (D / 4)], ta);
+        }
+        wave_lds_sync();
+        // ---- Y^T = [U; W]^T [X | T]^T on MFMA, lane gets row l % 16
+        {
+            f32x4 o[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) o[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk) {
+                const float a = As[wv][lane % 16][kk * 4 + lane / 16];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    o[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sW[(kk * NT + nt) * WAVE + lane], a,
+                                                                 o[nt], 0, 0, 0);
+            }
+            const int64_t r = r0 + lane % 16;
+            if constexpr (!DEC) {
+                if (r < rows) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        *reinterpret_cast<float4 *>(Y + r * D + nt * 16 + 4 * (lane / 16)) =
+                            make_float4(relu(o[nt][0]), relu(o[nt][1]), relu(o[nt][2]),
+                                        relu(o[nt][3]));
+                }
+            } else {
+                // ---- decoder: Y to LDS, hidden^T = W3^T Y^T on MFMA, then
+                // ReLU(. + c3) W4 per row
+                wave_lds_sync();
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int f = nt * 16 + 4 * (lane / 16);
+                    *reinterpret_cast<float4 *>(&As[wv][lane % 16][f]) =
+                        make_float4(relu(o[nt][0]), relu(o[nt][1]), relu(o[nt][2]), relu(o[nt][3]));
+                }
+                wave_lds_sync();
+                f32x4 hacc[H / 16];
+#pragma unroll
+                for (int nt = 0; nt < H / 16; ++nt) hacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kk = 0; kk < D / 4; ++kk) {
+                    const float y = As[wv][lane % 16][kk * 4 + lane / 16];
+#pragma unroll
+                    for (int nt = 0; nt < H / 16; ++nt)
+                        hacc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            sW3[(kk * (H / 16) + nt) * WAVE + lane], y, hacc[nt], 0, 0, 0);
+                }
+                float part = 0.f;
+#pragma unroll
+                for (int nt = 0; nt < H / 16; ++nt) {
+                    const int k0 = nt * 16 + 4 * (lane / 16);
+                    const float4 c3 = *reinterpret_cast<const float4 *>(&sC3[k0]);
+                    const float4 w4 = *reinterpret_cast<const float4 *>(&sW4[k0]);
+                    part += fmaxf(hacc[nt][0] + c3.x, 0.f) * w4.x;
+                    part += fmaxf(hacc[nt][1] + c3.y, 0.f) * w4.y;
+                    part += fmaxf(hacc[nt][2] + c3.z, 0.f) * w4.z;
+                    part += fmaxf(hacc[nt][3] + c3.w, 0.f) * w4.w;
+                }
+                part += __shfl_xor(part, 16, WAVE);
+                part += __shfl_xor(part, 32, WAVE);
+                if (lane < 16 && r < rows)
+                    z[r] = (ZT)(tau[3 * ((uint32_t)r % (uint32_t)B) + 2] *
+                                (double)(part + vec[oc4]));
+            }
+        }
+        commit(cnt1, cv1, av1);
+        int32_t kb2, cnt2;
+        slice_range(t + 2 * nw, rp2, kb2, cnt2);
+        wave_lds_sync();
+        rp0 = rp1;
+        rp1 = rp2;
+        kb0 = kb1;
+        cnt0 = cnt1;
+        kb1 = kb2;
+        cnt1 = cnt2;
+    }
+}
+
 #define GNP_LAYER_PARAMS                                                                       \
     int64_t rows, int B, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,       \
         const typename Act<G>::vt *__restrict__ ahat, const G *__restrict__ X,                 \
@@ -1044,6 +1307,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
     layer_tiles_bf16<D, H, DEC, B1, SHORT, ZT>(rows, B, rp, ci, ahat, X, Y, wcat, w3, vec, oc3, oW4,
                                                oc4, tau, z, skip);
 }
+// The pipelined float32 layers, held to 128 registers (4 wavefronts per SIMD).
+template <typename G, int D, int H, bool DEC, typename ZT, bool B1 = false, bool SHORT = false>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_layer_f32p(
+    GNP_LAYER_PARAMS) {
+    static_assert(sizeof(G) == 4, "float32 layer");
+    layer_tiles_f32p<D, H, DEC, B1, SHORT, ZT>(rows, B, rp, ci, ahat, X, Y, wcat, w3, vec, oc3,
+                                               oW4, oc4, tau, z, skip);
+}
+
 #undef GNP_LAYER_PARAMS
 #undef GNP_LAYER_ARGS
 
@@ -1063,6 +1335,13 @@ inline void (*layer_kernel(int B = 0, int max_row = 0))(
                         : &k_layer_w4<G, D, H, DEC, ZT, true, false>;
         return shrt ? &k_layer_w4<G, D, H, DEC, ZT, false, true>
                     : &k_layer_w4<G, D, H, DEC, ZT, false, false>;
+    } else if constexpr (sizeof(G) == 4) {
+        const bool shrt = max_row > 0 && max_row <= 7;
+        if (B == 1)
+            return shrt ? &k_layer_f32p<G, D, H, DEC, ZT, true, true>
+                        : &k_layer_f32p<G, D, H, DEC, ZT, true, false>;
+        return shrt ? &k_layer_f32p<G, D, H, DEC, ZT, false, true>
+                    : &k_layer_f32p<G, D, H, DEC, ZT, false, false>;
     } else {
         return &k_layer<G, D, H, DEC, ZT>;
     }
@@ -1082,6 +1361,14 @@ inline int layer_grid(int64_t rows, int B = 0, int max_row = 0) {
         else
             resident = shrt ? resident_blocks<&k_layer_w4<G, D, H, DEC, ZT, false, true>>()
                             : resident_blocks<&k_layer_w4<G, D, H, DEC, ZT, false, false>>();
+    } else if constexpr (sizeof(G) == 4) {
+        const bool shrt = max_row > 0 && max_row <= 7;
+        if (B == 1)
+            resident = shrt ? resident_blocks<&k_layer_f32p<G, D, H, DEC, ZT, true, true>>()
+                            : resident_blocks<&k_layer_f32p<G, D, H, DEC, ZT, true, false>>();
+        else
+            resident = shrt ? resident_blocks<&k_layer_f32p<G, D, H, DEC, ZT, false, true>>()
+                            : resident_blocks<&k_layer_f32p<G, D, H, DEC, ZT, false, false>>();
     } else {
         resident = resident_blocks<&k_layer<G, D, H, DEC, ZT>>();
     }

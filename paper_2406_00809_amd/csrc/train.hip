@@ -550,13 +550,21 @@ static void fwd_save(gnp_model *m, TrainCtx *c, const T *bin, T *z, hipStream_t 
         w2 = m->pk_f32 + m->pf.W2;
         ahat = (const T *)s->ahat32;
     }
-    hipLaunchKernelGGL((k_encoder<T, T, D, H>), dim3(grid), dim3(BLOCK), 0, st, rows, B, bin,
-                       c->tau, vec, po.W1, po.c1, po.c2, w2, acts, (const int *)nullptr);
+    if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((k_encoder<T, T, D, H>), dim3(grid), dim3(BLOCK), 0, st, rows, B, bin,
+                           c->tau, vec, po.W1, po.c1, po.c2, w2, acts, (const int *)nullptr);
+    } else {  // the persistent MFMA encoder of the apply path
+        const int ge = std::min(grid, resident_blocks<k_encoder_p<T, T, D, H>>());
+        hipLaunchKernelGGL((k_encoder_p<T, T, D, H>), dim3(ge), dim3(BLOCK), 0, st, rows, B, bin,
+                           c->tau, vec, po.W1, po.c1, po.c2, w2, acts, (const int *)nullptr,
+                           BasisNext{}, s->n);
+    }
     for (int l = 0; l < m->L; ++l) {
         const void *wc;
         if constexpr (sizeof(T) == 8) wc = m->theta64 + po.U0 + (int64_t)l * 2 * D * D;
         else wc = m->pk_f32 + m->pf.Wcat0 + l * m->pf.Wcat_stride;
-        hipLaunchKernelGGL((layer_kernel<T, D, H, false, T>()), dim3(layer_grid<T, D, H, false, T>(rows)),
+        hipLaunchKernelGGL((layer_kernel<T, D, H, false, T>(B, s->max_row)),
+                           dim3(layer_grid<T, D, H, false, T>(rows, B, s->max_row)),
                            dim3(BLOCK), 0, st, rows, B,
                            s->rp, s->ci, ahat, acts + (int64_t)l * rows * D,
                            acts + (int64_t)(l + 1) * rows * D, wc, (const void *)nullptr, vec,
