@@ -136,13 +136,13 @@ def layer_traffic(prec):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def serve_bench(args):
-    """Serving workload: a fleet of resident systems of four families with
-    log-uniform sizes, each with a trained network; Poisson arrivals of solve
-    requests for uniformly chosen systems; continuous batching in the server.
-    Saturation throughput (all requests queued at once) first, then a sweep of
-    arrival rates below and above it, and the same requests solved one at a
-    time with the float32 network for comparison."""
+def serve_fleet(args):
+    """The serving fleet: systems of four families (2D / 3D Laplace, 3D
+    convection-diffusion, power-law random; one after the other), n drawn
+    log-uniform in [4096, serve_nmax] (seed 6) and snapped to a grid size,
+    each with a network trained on its own matrix (batch serve_batch, fresh
+    x ~ N(0, I) per step).  With --serve-cache the trained weights are read
+    from / written to that .npz file (keyed by system name and size)."""
     import math
 
     import numpy as np
@@ -150,11 +150,14 @@ def serve_bench(args):
     from paper_2406_00809_amd import api
     from paper_2406_00809_amd import inputs as I
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    L, d, h, m, rtol = 8, 32, 64, 30, 1e-8
+    L, d, h = 8, 32, 64
     rng = np.random.default_rng(6)
     fams = ["laplace2d", "laplace3d", "convdiff3d", "powerlaw"]
-    fleet = []
+    cache = {}
+    if args.serve_cache and os.path.exists(args.serve_cache):
+        with np.load(args.serve_cache, allow_pickle=False) as z:
+            cache = {k: z[k] for k in z.files}
+    fleet, trained = [], {}
     t0 = time.perf_counter()
     for k in range(args.serve_systems):
         fam = fams[k % 4]
@@ -167,23 +170,57 @@ def serve_bench(args):
             A = I.convdiff3d(max(4, round(nt ** (1 / 3))))
         else:
             A = I.powerlaw_random(int(nt), seed_structure=100 + k, seed_values=200 + k)
+        name = f"{k:02d}_{fam}_n{A.n}_t{args.serve_train_steps}_b{args.serve_batch}"
         S = api.System(A)
-        M = api.Model(S, L, d, h, I.init_params(L, d, h, 300 + k))
-        M.train(args.serve_train_steps, 16, lr=1e-3, seed=400 + k, prec="f32")
-        fleet.append((f"{fam}_n{A.n}", A, S, M))
+        if name in cache:
+            M = api.Model(S, L, d, h, cache[name])
+        else:
+            M = api.Model(S, L, d, h, I.init_params(L, d, h, 300 + k))
+            M.train(args.serve_train_steps, args.serve_batch, lr=1e-3, seed=400 + k, prec="f32")
+            trained[name] = M.get_params()
+            log(f"trained {name} ({time.perf_counter() - t0:.0f}s)")
+        fleet.append((name, A, S, M))
     torch.cuda.synchronize()
-    log(f"fleet of {len(fleet)} systems trained in {time.perf_counter() - t0:.1f}s: "
+    train_s = time.perf_counter() - t0
+    if trained and args.serve_cache:
+        cache.update(trained)
+        np.savez(args.serve_cache, **cache)
+    return fleet, train_s, len(trained)
+
+
+def serve_bench(args):
+    """Serving workload: the fleet of serve_fleet resident in the server;
+    serve_requests requests b ~ N(0, I) (seed 1000 + id) for uniformly chosen
+    systems (seed 8); continuous batching.  Saturation (all requests queued
+    at once) first, then Poisson arrivals (exponential gaps, seed 7) at 0.5,
+    0.7, 0.9 and 1.1 x the saturation rate, the saturation run again under a
+    2 GiB HBM budget (admission binds), and the same requests solved one at a
+    time with the float32 network.  Throughput and latency percentiles count
+    the converged requests (true residual <= rtol); requests that stop at
+    maxiters are reported apart."""
+    import numpy as np
+    import torch
+    from paper_2406_00809_amd import api
+    from paper_2406_00809_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    m, rtol = 30, 1e-8
+    fleet, train_s, ntrained = serve_fleet(args)
+    log(f"fleet of {len(fleet)} systems ready in {train_s:.1f}s ({ntrained} trained here): "
         + ", ".join(f[0] for f in fleet))
+    if args.serve_train_only:
+        print(json.dumps({"fleet": [f[0] for f in fleet], "train_s": train_s,
+                          "trained": ntrained}), flush=True)
+        return
 
     nreq = args.serve_requests
     pick = np.random.default_rng(8).integers(0, len(fleet), nreq)
     bs = [I.rhs_normal(fleet[s][1].n, 1000 + i) for i, s in enumerate(pick)]
 
-    def run(rate):
+    def run(rate, budget_gb):
         """Submit the requests (all at once when rate is None, else Poisson
         arrivals at `rate` per second); return throughput and latencies."""
-        srv = api.Server(args.serve_budget_gb << 30, args.serve_slots, m, args.maxiters,
-                         prec=args.prec)
+        srv = api.Server(budget_gb << 30, args.serve_slots, m, args.maxiters, prec=args.prec)
         ids = [srv.register(S, M) for _, _, S, M in fleet]
         gaps = np.random.default_rng(7).exponential(1.0 / rate, nreq) if rate else np.zeros(nreq)
         tickets = {}
@@ -194,52 +231,92 @@ def serve_bench(args):
             while time.perf_counter() < t_next:
                 time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
             tickets[srv.submit(ids[pick[i]], bs[i], rtol=rtol, maxiters=args.maxiters)] = i
-        srv.drain(3600.0)
+        while True:  # drain, reporting progress every 20 s
+            try:
+                srv.drain(20.0)
+                break
+            except api.GNPError:
+                st = srv.stats()
+                log(f"  ... {st['completed']} of {nreq} done ({st['converged']} converged), "
+                    f"{time.perf_counter() - t_start:.0f}s")
         wall = time.perf_counter() - t_start
-        conv, its = 0, []
+        its, unconv, per = [], {}, {}
         for t, i in tickets.items():
             x, info, lat = srv.poll(t, fleet[pick[i]][1].n)
-            conv += info["converged"]
             its.append(info["iters"])
+            nm = fleet[pick[i]][0]
+            p = per.setdefault(nm, [0, 0, 0])  # requests, converged, iterations
+            p[0] += 1
+            p[1] += info["converged"]
+            p[2] += info["iters"]
+            if not info["converged"]:
+                unconv[nm] = unconv.get(nm, 0) + 1
         st = srv.stats()
         srv.close()
-        return {"offered_per_s": rate, "solves_per_s": nreq / wall,
-                "latency_p50_ms": 1e3 * st["latency_p50_s"],
-                "latency_p99_ms": 1e3 * st["latency_p99_s"],
-                "converged": conv, "requests": nreq, "mean_iters": float(np.mean(its)),
+        return {"offered_per_s": rate, "hbm_budget_gb": budget_gb,
+                "converged_per_s": st["converged"] / wall,
+                "all_completed_per_s": st["completed"] / wall,
+                "converged": st["converged"], "not_converged": nreq - st["converged"],
+                "not_converged_by_system": unconv, "requests": nreq,
+                "per_system": {k: {"requests": v[0], "converged": v[1],
+                                   "mean_iters": v[2] / v[0]} for k, v in sorted(per.items())},
+                "latency_p50_ms": 1e3 * st["conv_latency_p50_s"],
+                "latency_p99_ms": 1e3 * st["conv_latency_p99_s"],
+                "latency_all_p50_ms": 1e3 * st["latency_p50_s"],
+                "latency_all_p99_ms": 1e3 * st["latency_p99_s"],
+                "mean_iters": float(np.mean(its)), "wall_s": wall,
                 "max_active": st["max_active"], "hbm_peak_gb": st["hbm_peak"] / 2 ** 30,
                 "workspaces_reused": st["workspaces_reused"],
                 "workspaces_evicted": st["workspaces_evicted"]}
 
-    sat = run(None)
-    log(f"saturation: {sat}")
+    parts = set(args.serve_parts.split(","))
+    sat = None
+    if "sat" in parts or not args.serve_sat_rate:
+        sat = run(None, args.serve_budget_gb)
+        log(f"saturation: {sat}")
     sweep = []
-    for frac in (0.5, 0.7, 0.9, 1.1):
-        r = run(frac * sat["solves_per_s"])
-        log(f"offered {frac:.1f} x saturation: {r}")
-        sweep.append(r)
+    if "sweep" in parts:
+        # offered rates relative to the saturation throughput of all requests
+        # (converged or not: every request occupies the server)
+        rate0 = args.serve_sat_rate or sat["all_completed_per_s"]
+        for frac in (float(f) for f in args.serve_sweep.split(",")):
+            r = run(frac * rate0, args.serve_budget_gb)
+            r["offered_fraction"] = frac
+            log(f"offered {frac:.2f} x saturation: {r}")
+            sweep.append(r)
+    small = None
+    if "budget2" in parts:
+        small = run(None, 2)
+        log(f"saturation under a 2 GiB budget: {small}")
 
     # the same requests one at a time, float32 network, fgmres_solve
-    t1 = time.perf_counter()
-    conv32 = 0
-    for i in range(nreq):
-        _, A, S, M = fleet[pick[i]]
-        b = torch.as_tensor(bs[i], dtype=torch.float64, device="cuda")
-        _, info, _ = api.fgmres_solve(S, b, M, m=m, rtol=rtol, maxiters=args.maxiters,
-                                      prec="f32", want_hist=False)
-        conv32 += info["converged"]
-    torch.cuda.synchronize()
-    seq32 = nreq / (time.perf_counter() - t1)
-    log(f"float32 single solves one at a time: {seq32:.2f} solves/s, {conv32} converged")
+    conv32, el32 = 0, float("nan")
+    if "fp32" in parts:
+        t1 = time.perf_counter()
+        t_log = t1
+        for i in range(nreq):
+            _, A, S, M = fleet[pick[i]]
+            b = torch.as_tensor(bs[i], dtype=torch.float64, device="cuda")
+            _, info, _ = api.fgmres_solve(S, b, M, m=m, rtol=rtol, maxiters=args.maxiters,
+                                          prec="f32", want_hist=False)
+            conv32 += info["converged"]
+            if time.perf_counter() - t_log > 20.0:
+                t_log = time.perf_counter()
+                log(f"  ... float32 one at a time: {i + 1} of {nreq} ({conv32} converged), "
+                    f"{t_log - t1:.0f}s")
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t1
+        log(f"float32 single solves one at a time: {conv32 / el32:.2f} converged solves/s, "
+            f"{conv32} of {nreq} converged")
 
     out = {
-        "metric": "served GNP-FGMRES solves/s to rtol 1e-8 (saturation), p50/p99 latency",
-        "value": sat["solves_per_s"],
+        "metric": "served GNP-FGMRES converged solves/s to rtol 1e-8 (saturation), p50/p99 latency",
+        "value": sat["converged_per_s"] if sat else None,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": nreq,
         "warmup": 0,
-        "ms_per_step": 1e3 / sat["solves_per_s"],
+        "ms_per_step": 1e3 / max(sat["converged_per_s"], 1e-12) if sat else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -248,14 +325,17 @@ def serve_bench(args):
         "config": {
             "workload": (f"serving: {len(fleet)} resident systems (2D/3D Laplace, 3D "
                          f"convection-diffusion, power-law random; n log-uniform in "
-                         f"[4096, {args.serve_nmax}]), GNP L={L} d={d} h={h} trained "
-                         f"{args.serve_train_steps} steps batch 16 each; {nreq} requests "
-                         f"b ~ N(0, I), uniform system choice; FGMRES({m}) rtol 1e-8, "
-                         f"{args.serve_slots} slots, HBM budget {args.serve_budget_gb} GiB"),
+                         f"[4096, {args.serve_nmax}]), GNP L=8 d=32 h=64 trained "
+                         f"{args.serve_train_steps} steps batch {args.serve_batch} each; "
+                         f"{nreq} requests b ~ N(0, I), uniform system choice; FGMRES({m}) "
+                         f"rtol 1e-8, maxiters {args.maxiters}, {args.serve_slots} slots, HBM "
+                         f"budget {args.serve_budget_gb} GiB"),
             "systems": [f[0] for f in fleet],
+            "fleet_train_s": train_s,
             "saturation": sat,
             "poisson_sweep": sweep,
-            "fp32_single_solve_sequential_solves_per_s": seq32,
+            "saturation_budget_2GiB": small,
+            "fp32_single_solve_sequential_converged_per_s": conv32 / el32,
             "fp32_single_solve_converged": conv32,
         },
     }
@@ -286,12 +366,25 @@ def main():
                          "no training or solves")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: continuous batching over a fleet of systems")
-    ap.add_argument("--serve-systems", type=int, default=8)
+    ap.add_argument("--serve-systems", type=int, default=40)
     ap.add_argument("--serve-nmax", type=int, default=500000)
-    ap.add_argument("--serve-train-steps", type=int, default=200)
-    ap.add_argument("--serve-requests", type=int, default=200)
-    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-train-steps", type=int, default=2000)
+    ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=int, default=32)
+    ap.add_argument("--serve-cache", default="",
+                    help=".npz file of the fleet's trained weights (read if present, written "
+                         "after training)")
+    ap.add_argument("--serve-train-only", action="store_true",
+                    help="train (or load) the fleet and stop")
+    ap.add_argument("--serve-parts", default="sat,sweep,budget2,fp32",
+                    help="runs: sat (all requests queued at once), sweep (Poisson arrivals at "
+                         "--serve-sweep x the saturation rate), budget2 (saturation under 2 GiB), "
+                         "fp32 (the same requests one at a time, float32 network)")
+    ap.add_argument("--serve-sweep", default="0.5,0.7,0.9,1.1")
+    ap.add_argument("--serve-sat-rate", type=float, default=0.0,
+                    help="saturation rate (requests/s) for the sweep; 0: measure it first")
     ap.add_argument("--sampler-compare", action="store_true",
                     help="also train a network with the Arnoldi sampler of Eq. (3) (m = 40, "
                          "half of every batch) and report its iterations and solves/s")
