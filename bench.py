@@ -226,11 +226,17 @@ def serve_bench(args):
         tickets = {}
         t_start = time.perf_counter()
         t_next = t_start
+        t_log = t_start
         for i in range(nreq):
             t_next += gaps[i]
             while time.perf_counter() < t_next:
                 time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
             tickets[srv.submit(ids[pick[i]], bs[i], rtol=rtol, maxiters=args.maxiters)] = i
+            if time.perf_counter() - t_log > 20.0:
+                t_log = time.perf_counter()
+                st = srv.stats()
+                log(f"  ... {i + 1} of {nreq} submitted, {st['completed']} done "
+                    f"({st['converged']} converged), {t_log - t_start:.0f}s")
         while True:  # drain, reporting progress every 20 s
             try:
                 srv.drain(20.0)

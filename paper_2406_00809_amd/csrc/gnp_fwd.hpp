@@ -229,7 +229,9 @@ __global__ __launch_bounds__(BLOCK) void k_encoder(int64_t rows, int B, const IN
 // bn.V, w - V[:, 0..j] h first, in the solver's correction arithmetic (8
 // lanes per row, lane q owning columns 4q..4q+3, FP64 products summed in
 // column order, then across the 8 lanes by xor 1, 2, 4), then the division
-// by *hdiv.  v is written to bn.vout; its tau of Eq. (6) is 1 (v has unit
+// by *hdiv.  v is written to bn.vout and, with bn.Vout, into column j + 1 of
+// the basis (the lane holding that column stores its four columns whole); its
+// tau of Eq. (6) is 1 (v has unit
 // norm), and block 0 publishes that triple for the decoder.
 // ---------------------------------------------------------------------------
 template <typename G, typename IN, int D, int H>
@@ -341,6 +343,18 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
                 if (cq == 0) {
                     s_vb[wv][8 * rho + lane / 8] = vb;
                     if (bn.vout && r < rows) bn.vout[r] = vb;
+                }
+                // the basis column j + 1: the lane holding it writes its four
+                // columns back whole (one 16-byte store; the columns past
+                // j + 1 keep what they held)
+                if (bn.Vout && cq == ((bn.j + 1) >> 2) && r < rows) {
+                    float4 nv = vq[rho];
+                    const int e = (bn.j + 1) & 3;
+                    nv.x = e == 0 ? (float)vb : nv.x;
+                    nv.y = e == 1 ? (float)vb : nv.y;
+                    nv.z = e == 2 ? (float)vb : nv.z;
+                    nv.w = e == 3 ? (float)vb : nv.w;
+                    *reinterpret_cast<float4 *>(bn.Vout + r * 32 + 4 * cq) = nv;
                 }
             }
             load_corr(t + nw);  // the next tile's rows (clamped past the end)

@@ -108,6 +108,7 @@ struct BasisNext {
     float *vout = nullptr;         // v, the solver's contiguous copy
     const float *V = nullptr;      // basis (pitch 32); nullptr: w is already final
     const double *h = nullptr;     // correction coefficients h[0..j]
+    float *Vout = nullptr;         // with V: also store v as column j + 1 of the basis
     int j = 0;
 };
 

@@ -368,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                                                double *__restrict__ partial, int pstride,
                                                const Ctl *ctl, Bat bt,
                                                const KT *__restrict__ vcur,
-                                               KT *__restrict__ vout) {
+                                               KT *__restrict__ vout, int vj_in_V = 0) {
     ctl += blockIdx.y;
     // the end-of-cycle flag is tested only after the first round of loads
     // has been issued (the loads are in bounds either way), so its latency
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                 }
             }
             wold[ru] = w[ic];
-            if (MODE == 0) vj[ru] = vcur[ic * bt.vstep];
+            if (MODE == 0 && !vj_in_V) vj[ru] = vcur[ic * bt.vstep];
         }
         if (first) {
             if (done) return;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
         for (int ru = 0; ru < RU; ++ru) {
             const int64_t i = ib + (int64_t)ru * RPP;
             const bool ok = i < i1;
-            if (MODE == 0) {
+            if (MODE == 0 && !vj_in_V) {  // column j from vcur, stored into the basis
 #pragma unroll
                 for (int a = 0; a < NA; ++a)
                     if (4 * (q + 8 * (a / 4)) + a % 4 == j) v[ru][a] = vj[ru];
@@ -850,6 +850,8 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                 bn.V = (const float *)V;
                 bn.h = c->h2;
                 bn.j = j - 1;
+                bn.Vout = (float *)V;  // v_j into column j of the basis ...
+                bn.vout = nullptr;     // ... which the first pass then reads as it is
             }
         }
         if (model)
@@ -877,7 +879,8 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                                 s->max_row);
         hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
-                           Bat{}, (const KT *)vcur, (KT *)nullptr);
+                           Bat{}, (const KT *)vcur, (KT *)nullptr,
+                           (int)(fuse && corr_in_encoder));
         hipLaunchKernelGGL(k_fin_dots, dim3(j + 2), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, Bat{});
         hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
