@@ -344,8 +344,22 @@ __global__ void k_unit_tau(int64_t n, double *tau, const Ctl *ctl, int *all_done
 // w -= V_j hprev only (its norm follows from MODE 1's sums, k_fin_givens).
 // MODE 3 (one right-hand side): MODE 2, and the next basis vector
 // v_{j+1} = w / h_{j+1,j} into vout with the expression of k_normalize.
+// MODE 4: MODE 0 with the SpMV w = A z_j fused in front: the eight lanes of a
+// row take its nonzeros q, q + 8, ... in order (FP32 products and sums, FP64
+// for a float64 basis), add their partial sums across the lanes by xor 4, 2,
+// 1, and lane 0 stores w_i; the dots then use w_i as MODE 0 uses w.
 // Entries k > j are masked by selection (they may hold an older cycle).
 // ---------------------------------------------------------------------------
+// The SpMV operands of the first pass when it forms w = A z_j itself
+// (MODE 4): CSR of the system matrix in the Krylov precision and z_j, read
+// at ci * zstep + (right-hand side) for a batch whose network outputs are
+// packed [n][nb].
+template <typename KT> struct SpIn {
+    const int32_t *rp = nullptr, *ci = nullptr;
+    const KT *val = nullptr, *z = nullptr;
+    int64_t zstep = 1;
+};
+
 template <typename KT> struct Quad;
 template <> struct Quad<float> {
     static __device__ __forceinline__ void load_raw(const float *p, float *o) {
@@ -368,15 +382,18 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                                                double *__restrict__ partial, int pstride,
                                                const Ctl *ctl, Bat bt,
                                                const KT *__restrict__ vcur,
-                                               KT *__restrict__ vout, int vj_in_V = 0) {
+                                               KT *__restrict__ vout, int vj_in_V = 0,
+                                               SpIn<KT> sp = SpIn<KT>()) {
     ctl += blockIdx.y;
     // the end-of-cycle flag is tested only after the first round of loads
     // has been issued (the loads are in bounds either way), so its latency
     // overlaps theirs
     const int done = ctl->cycle_done;
+    constexpr bool D0 = MODE == 0 || MODE == 4;  // the first pass (dots, column j)
     V += blockIdx.y * bt.basis;
     w += blockIdx.y * bt.vec;
-    if (MODE == 0) vcur += blockIdx.y;
+    if (D0) vcur += blockIdx.y;
+    if (MODE == 4) sp.z += blockIdx.y;
     if (hprev) hprev += blockIdx.y * bt.small;
     partial += blockIdx.y * bt.part;
     constexpr int NU = MP / 32, NA = 4 * NU;
@@ -388,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
     for (int a = 0; a < NA; ++a) {
         acc[a] = 0.0;
         const int k = 4 * (q + 8 * (a / 4)) + a % 4;
-        hp[a] = (MODE >= 1 && k <= j) ? hprev[k] : 0.0;
+        hp[a] = (MODE >= 1 && MODE <= 3 && k <= j) ? hprev[k] : 0.0;
     }
     double nrm = 0.0;
     // every row of the block in one round of loads (rpb = RPP * RU)
@@ -398,13 +415,19 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
     const bool owner_j = q == ((j >> 2) & 7);
     double hdiv = 1.0;
     bool first = true;
+    using Acc = typename std::conditional<sizeof(KT) == 8, double, float>::type;
     for (int64_t ib = i0 + g; ib < i1; ib += (int64_t)RPP * RU) {
         KT v[RU][NA];
         KT wold[RU], vj[RU];
+        int32_t kb[RU], ke[RU];
 #pragma unroll
         for (int ru = 0; ru < RU; ++ru) {
             const int64_t i = ib + (int64_t)ru * RPP;
             const int64_t ic = i < i1 ? i : i1 - 1;
+            if (MODE == 4) {
+                kb[ru] = sp.rp[ic];
+                ke[ru] = sp.rp[ic + 1];
+            }
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int c = q + 8 * u;
@@ -415,8 +438,34 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                     for (int e = 0; e < 4; ++e) v[ru][4 * u + e] = (KT)0;
                 }
             }
-            wold[ru] = w[ic];
-            if (MODE == 0 && !vj_in_V) vj[ru] = vcur[ic * bt.vstep];
+            if (MODE != 4) wold[ru] = w[ic];
+            if (D0 && !vj_in_V) vj[ru] = vcur[ic * bt.vstep];
+        }
+        if (MODE == 4) {
+            // w_i = (A z)_i: every lane's first nonzero in flight for all rows,
+            // then the rest of longer rows
+            int32_t cc[RU];
+            KT av[RU];
+#pragma unroll
+            for (int ru = 0; ru < RU; ++ru) {
+                const int32_t k = kb[ru] + q;
+                const int32_t kk = k < ke[ru] ? k : (ke[ru] > 0 ? ke[ru] - 1 : 0);
+                cc[ru] = sp.ci[kk];
+                av[ru] = sp.val[kk];
+            }
+            KT xv[RU];
+#pragma unroll
+            for (int ru = 0; ru < RU; ++ru) xv[ru] = sp.z[(int64_t)cc[ru] * sp.zstep];
+#pragma unroll
+            for (int ru = 0; ru < RU; ++ru) {
+                Acc p = kb[ru] + q < ke[ru] ? (Acc)av[ru] * (Acc)xv[ru] : (Acc)0;
+                for (int32_t k = kb[ru] + q + 8; k < ke[ru]; k += 8)
+                    p += (Acc)sp.val[k] * (Acc)sp.z[(int64_t)sp.ci[k] * sp.zstep];
+                p += __shfl_xor(p, 4, WAVE);
+                p += __shfl_xor(p, 2, WAVE);
+                p += __shfl_xor(p, 1, WAVE);
+                wold[ru] = (KT)p;
+            }
         }
         if (first) {
             if (done) return;
@@ -427,7 +476,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
         for (int ru = 0; ru < RU; ++ru) {
             const int64_t i = ib + (int64_t)ru * RPP;
             const bool ok = i < i1;
-            if (MODE == 0 && !vj_in_V) {  // column j from vcur, stored into the basis
+            if (D0 && !vj_in_V) {  // column j from vcur, stored into the basis
 #pragma unroll
                 for (int a = 0; a < NA; ++a)
                     if (4 * (q + 8 * (a / 4)) + a % 4 == j) v[ru][a] = vj[ru];
@@ -440,7 +489,8 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                 vv[a] = (k <= j) ? (double)v[ru][a] : 0.0;
             }
             double wi;
-            if (MODE == 0) {
+            if (D0) {
+                if (MODE == 4 && ok && q == 0) w[i] = wold[ru];
                 wi = ok ? (double)wold[ru] : 0.0;
             } else {
                 double corr = 0.0;
@@ -454,18 +504,18 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
                 if (MODE == 3 && ok && q == 0) vout[i] = (KT)((double)wn / hdiv);
                 wi = ok ? (double)wn : 0.0;
             }
-            if (MODE <= 1) {
+            if (MODE <= 1 || MODE == 4) {
 #pragma unroll
                 for (int a = 0; a < NA; ++a) acc[a] += vv[a] * wi;
             }
-            if (MODE <= 1 && q == 0) nrm += wi * wi;
+            if ((MODE <= 1 || MODE == 4) && q == 0) nrm += wi * wi;
         }
     }
-    if (done) return;                 // rows of no round (the tail block)
-    if constexpr (MODE >= 2) return;  // no sums
+    if (done) return;                              // rows of no round (the tail block)
+    if constexpr (MODE == 2 || MODE == 3) return;  // no sums
     __shared__ double sh[BLOCK / WAVE][8 * NA + 1];
     const int lane = t % WAVE, wv = t / WAVE;
-    if (MODE <= 1) {
+    if (MODE <= 1 || MODE == 4) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
             double s = acc[a];
@@ -481,7 +531,7 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
     }
     __syncthreads();
     double *dst = partial + (int64_t)blockIdx.x * pstride;
-    if (MODE <= 1) {
+    if (MODE <= 1 || MODE == 4) {
         for (int k = t; k <= j; k += BLOCK) {
             const int c = k / 4, e = k % 4, qq = c % 8, u = c / 8;
             double s = 0.0;
@@ -875,12 +925,16 @@ static gnp_status launch_cycle_mp(SolveCtx *c, gnp_model *model, int nsteps, dou
                 hipLaunchKernelGGL((k_inner_end<KT>), dim3(sg), dim3(BLOCK), 0, st, n,
                                    (const double *)xin, zj, (const Ctl *)c->ctl);
         }
-        spmv_launch<KT, KT, KT>(n, s->rp, s->ci, val, zj, w, nullptr, skip, s->nnz, st, 1, 1, 0, 0,
-                                s->max_row);
-        hipLaunchKernelGGL((k_cgs<KT, MP, 0>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
+        // w = A z_j and the first Gram-Schmidt pass in one kernel
+        SpIn<KT> sp;
+        sp.rp = s->rp;
+        sp.ci = s->ci;
+        sp.val = val;
+        sp.z = zj;
+        hipLaunchKernelGGL((k_cgs<KT, MP, 4>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
                            (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
                            Bat{}, (const KT *)vcur, (KT *)nullptr,
-                           (int)(fuse && corr_in_encoder));
+                           (int)(fuse && corr_in_encoder), sp);
         hipLaunchKernelGGL(k_fin_dots, dim3(j + 2), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, Bat{});
         hipLaunchKernelGGL((k_cgs<KT, MP, 1>), dim3(gcgs), dim3(BLOCK), 0, st, n, rpb, V, j, w,
@@ -1130,12 +1184,15 @@ static gnp_status batch_cycle(BatchCtx *c, gnp_model *model, int nsteps, double 
         float *zj = c->Zp + (int64_t)j * n * nb;
         GNP_TRY(forward_launch(model, c->prec, c->vpk, zj, nb, c->tau, c->act[0], c->act[1],
                                c->all_done, st));
-        spmv_launch<float, float, float>(n, s->rp, s->ci, s->val32, zj, w, nullptr,
-                                         &c->ctl->cycle_done, s->nnz, st, nb, nb, n,
-                                         (int)(sizeof(Ctl) / sizeof(int)), s->max_row);
-        hipLaunchKernelGGL((k_cgs<float, MP, 0>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
+        SpIn<float> sp;  // z_j packed [n][nb]
+        sp.rp = s->rp;
+        sp.ci = s->ci;
+        sp.val = s->val32;
+        sp.z = zj;
+        sp.zstep = nb;
+        hipLaunchKernelGGL((k_cgs<float, MP, 4>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
                            w, (const double *)nullptr, c->partial, pstride, (const Ctl *)c->ctl,
-                           bt, (const float *)c->vpk, (float *)nullptr);
+                           bt, (const float *)c->vpk, (float *)nullptr, 0, sp);
         hipLaunchKernelGGL(k_fin_dots, dim3(j + 2, nb), dim3(BLOCK), 0, st, gcgs, j,
                            (const double *)c->partial, pstride, c->h1, c->ctl, bt);
         hipLaunchKernelGGL((k_cgs<float, MP, 1>), dim3(gcgs, nb), dim3(BLOCK), 0, st, n, rpb, V, j,
