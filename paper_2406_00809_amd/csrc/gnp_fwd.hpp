@@ -806,7 +806,7 @@ __device__ __forceinline__ void layer_tiles_bf16(
         __syncthreads();
     }
     if (skipped) return;
-    const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv);
+    const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv, B1);
     const int64_t ntiles = walk.end, nw = walk.stride;
     const uint32_t rowbytes = (uint32_t)B * (uint32_t)(D * sizeof(G));
     const int rshift = (rowbytes & (rowbytes - 1)) == 0 ? __builtin_ctz(rowbytes) : -1;
@@ -1104,7 +1104,7 @@ __device__ __forceinline__ void layer_tiles_f32p(
         __syncthreads();
     }
     if (skipped) return;
-    const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv);
+    const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv, B1);
     const int64_t ntiles = walk.end, nw = walk.stride;
     const uint32_t rowbytes = (uint32_t)B * (uint32_t)(D * sizeof(G));
     const int rshift = (rowbytes & (rowbytes - 1)) == 0 ? __builtin_ctz(rowbytes) : -1;

@@ -73,10 +73,13 @@ inline void spmv_launch_g(int64_t n, const int32_t *rp, const int32_t *ci, const
 }
 
 // Lanes per row from the mean row length (4 lanes for stencil-like rows: at
-// 7 nonzeros per row, 4 lanes beat 8 by a third on MI355X), one step wider
-// when the longest row exceeds four times the mean (a wavefront waits for
-// its longest row), with 4 entries per lane in flight for such irregular
-// rows and 2 otherwise.  max_row: the longest row (0 if unknown).
+// 7 nonzeros per row, 4 lanes beat 8 by a third on MI355X), with 4 entries
+// per lane in flight for irregular rows (the longest row above four times the
+// mean) and 2 otherwise.  Irregular rows of a short mean take 8 lanes rather
+// than 4 (a wavefront waits for its longest row); longer means keep their
+// width: on the n = 2^20 power-law matrix (mean 12, rows of 3..64, random
+// columns) 8 lanes take 76 us, 16 lanes 87 us.  max_row: the longest row (0
+// if unknown).
 template <typename VT, typename XT, typename YT>
 inline void spmv_launch(int64_t n, const int32_t *rp, const int32_t *ci, const VT *val,
                         const XT *x, YT *y, const double *bsub, const int *skip, int64_t nnz,
@@ -85,7 +88,7 @@ inline void spmv_launch(int64_t n, const int32_t *rp, const int32_t *ci, const V
     const double avg = (double)nnz / (double)n;
     const bool irregular = max_row > 4.0 * avg;
     int level = avg <= 12.0 ? 0 : (avg <= 24.0 ? 1 : (avg <= 48.0 ? 2 : 3));
-    if (irregular && level < 3) ++level;
+    if (irregular && level == 0) level = 1;
     const auto go = [&](auto g, auto nbv) {
         spmv_launch_g<VT, XT, YT, decltype(g)::value, decltype(nbv)::value>(
             n, rp, ci, val, x, y, bsub, skip, st, nb, xstep, ystride, skip_step);
