@@ -69,10 +69,42 @@ def test_loss_grad_matches_oracle(api, case, prec):
         assert el < 1e-5 and eg < 2e-3
 
 
-def _fd_check(M, th, b, prec, rng, ndir, h=1e-6):
+def _roundings(n, B, L, d, h, row_max):
+    """Roundings along one path from an input to the FP64 loss, counted
+    with every product and sum rounded once (FMA rounds less): the scaling
+    u = s b (1), the encoder's W1 u + c1 (2) and W2 with c2 (h + 1), per
+    layer A-hat X (row_max) and [X | T] [U; W] (2 d), the decoder's W3 with
+    c3 (d + 1), W4 with c4 (h + 1) and tau / sqrt(n) (1), the residual A z - b
+    (row_max + 1), and the mean of the n B absolute residuals as the loss
+    kernel adds them: a strided chain per thread over a grid of G =
+    min(ceil(nB / 256), 2048) blocks of 256, a 64-lane butterfly (6) and the
+    4 wavefronts (4), the same over the block partials, and the division."""
+    rows = n * B
+    G = min(-(-rows // 256), 2048)
+    d_sum = -(-rows // (G * 256)) + 10 + -(-G // 256) + 10 + 1
+    return (1 + 2 + (h + 1) + L * (row_max + 2 * d) + (d + 1) + (h + 1) + 1 + (row_max + 1)
+            + d_sum)
+
+
+def _fd_check(M, th, b, prec, rng, ndir, K, h=1e-6):
     """Central differences along random unit directions, with the Richardson
-    guard: a direction counts only when the h and h/2 quotients agree."""
+    guard: a direction counts only when the h and h/2 quotients agree.
+
+    Roundoff floor: the loss is computed with K roundings along each path
+    (_roundings).  In the probabilistic model of rounding errors (Higham and
+    Mary, SIAM J. Sci. Comput. 41 (2019)), K independent relative errors of
+    at most u = eps / 2 give a relative error below lambda sqrt(K) u except
+    with probability about 2 exp(-lambda^2 / 2); lambda = 6 (1.5e-8), with
+    |loss| as the scale of the sums (the loss is a mean of absolute values).
+    The worst-case bound, gamma_K times the loss of the network with
+    absolute weights, grows like the product of the layers' absolute gains
+    and is of no use here.  Each loss value then errs by at most
+    e = 6 sqrt(K) u |loss|, the h quotient by N = e / h, the h/2 quotient by
+    2 N: the two quotients may differ by 3 N from roundoff (4 N taken, the
+    rest for the O(h^2) terms), and the h quotient differs from g . v by N
+    (2 N taken) plus the gradient's own rounding (1e-6 relative)."""
     loss, g = M.loss_grad(b, prec=prec)
+    noise = 6.0 * np.sqrt(K) * (np.finfo(float).eps / 2) * abs(loss) / h
     used = 0
     for _ in range(4 * ndir):
         v = rng.standard_normal(th.size)
@@ -83,8 +115,6 @@ def _fd_check(M, th, b, prec, rng, ndir, h=1e-6):
             f[s] = M.loss_grad(b, prec=prec)[0]
         q1 = (f[h] - f[-h]) / (2 * h)
         q2 = (f[h / 2] - f[-h / 2]) / h
-        # roundoff of a central difference: ~ eps |loss| / h (absolute)
-        noise = 20 * np.finfo(float).eps * abs(loss) / h
         if abs(q1 - q2) > 4 * noise + 1e-7 * abs(q1):
             continue  # a ReLU or |.| kink lies inside the stencil
         used += 1
@@ -103,7 +133,8 @@ def test_finite_differences_gpu_f64(api):
     th = I.init_params(L, d, h, 23)
     M = api.Model(S, L, d, h, th)
     b = _dev(O.spmm(ref.A, np.random.default_rng(24).standard_normal((A.n, B))))
-    assert _fd_check(M, th, b, "f64", np.random.default_rng(25), 6) >= 6
+    K = _roundings(A.n, B, L, d, h, int(np.diff(A.rowptr).max()))
+    assert _fd_check(M, th, b, "f64", np.random.default_rng(25), 6, K) >= 6
 
 
 @pytest.mark.slow
@@ -117,7 +148,8 @@ def test_finite_differences_gpu_f64_full_training_shape(api):
     x = np.random.default_rng(26).standard_normal((A.n, B))
     b = _dev(A.to_scipy() @ x / S.gamma_input)
     t0 = time.time()
-    used = _fd_check(M, th, b, "f64", np.random.default_rng(27), 3)
+    K = _roundings(A.n, B, L, d, h, int(np.diff(A.rowptr).max()))
+    used = _fd_check(M, th, b, "f64", np.random.default_rng(27), 3, K)
     print(f"full-shape FD: {used} directions in {time.time() - t0:.1f}s")
     assert used >= 3
 
