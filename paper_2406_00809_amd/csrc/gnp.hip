@@ -99,9 +99,18 @@ __global__ __launch_bounds__(BLOCK) void k_colnorm(int64_t n, int B, int64_t chu
     if (p < S) {
         const int64_t i0 = (int64_t)blockIdx.x * chunk;
         const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
-        for (int64_t i = i0 + p; i < i1; i += S) {
-            const double x = (double)v[i * B + c];
-            s += x * x;
+        // eight rows in flight at once, squares added in row order
+        constexpr int U = 8;
+        for (int64_t ib = i0 + p; ib < i1; ib += U * S) {
+            double x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = ib + u * S < i1 ? ib + u * S : ib;
+                x[u] = (double)v[i * B + c];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ib + u * S < i1) s += x[u] * x[u];
         }
     }
     sh[t] = s;

@@ -72,15 +72,29 @@ __global__ __launch_bounds__(BLOCK) void k_loss(int64_t n, int B, const int32_t 
     const int64_t rows = n * B;
     double s = 0.0;
     const T inv = (T)(1.0 / (double)rows);
-    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < rows;
-         e += (int64_t)gridDim.x * BLOCK) {
-        const int64_t i = e / B;
-        const int k = (int)(e - i * B);
-        T acc = 0;
-        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) acc += val[q] * z[(int64_t)ci[q] * B + k];
-        const T r = acc - b[e];
-        S[e] = r > (T)0 ? inv : (r < (T)0 ? -inv : (T)0);
-        s += fabs((double)r);
+    // four rows of the thread's stride in flight at once; |r| is added in
+    // row order
+    constexpr int U = 4;
+    const int64_t step = (int64_t)gridDim.x * BLOCK;
+    for (int64_t e0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e0 < rows; e0 += U * step) {
+        T r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * step < rows ? e0 + u * step : e0;
+            const int64_t i = e / B;
+            const int k = (int)(e - i * B);
+            T acc = 0;
+            for (int32_t q = rp[i]; q < rp[i + 1]; ++q) acc += val[q] * z[(int64_t)ci[q] * B + k];
+            r[u] = acc - b[e];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + u * step;
+            if (e < rows) {
+                S[e] = r[u] > (T)0 ? inv : (r[u] < (T)0 ? -inv : (T)0);
+                s += fabs((double)r[u]);
+            }
+        }
     }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -390,13 +404,26 @@ __global__ __launch_bounds__(BLOCK) void k_enc_bwd(int64_t rows, int B, const T 
     }
 }
 
-// grad[p] = sum over blocks of gpart[blk * np + p], in block order
+// grad[p] = sum over blocks of gpart[blk * np + p], in block order; the
+// loads go out 16 at a time ahead of their adds (one round trip per 16
+// blocks instead of one per block), the adds keep the block order
 __global__ void k_grad_reduce(int64_t np, int nblk, const double *__restrict__ gpart,
                               double *__restrict__ grad) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
+    constexpr int U = 16;
     double a = 0.0;
-    for (int b = 0; b < nblk; ++b) a += gpart[(int64_t)b * np + p];
+    for (int b0 = 0; b0 < nblk; b0 += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u < nblk ? b0 + u : nblk - 1;
+            v[u] = gpart[(int64_t)b * np + p];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b0 + u < nblk) a += v[u];
+    }
     grad[p] = a;
 }
 
