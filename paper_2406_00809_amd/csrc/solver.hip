@@ -408,8 +408,9 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
         hp[a] = (MODE >= 1 && MODE <= 3 && k <= j) ? hprev[k] : 0.0;
     }
     double nrm = 0.0;
-    // every row of the block in one round of loads (rpb = RPP * RU)
-    constexpr int RU0 = (sizeof(KT) == 4 ? 16 : 8) * 32 / MP;
+    // every row of the block in one round of loads (rpb = RPP * RU at a
+    // basis pitch of 32)
+    constexpr int RU0 = 8 * 32 / MP;
     constexpr int RU = RU0 < 2 ? 2 : RU0;
     // the lane owning column j (MODE 0 stores it)
     const bool owner_j = q == ((j >> 2) & 7);
@@ -776,9 +777,12 @@ static int basis_pitch(int m) {
 }
 
 // rows per block of the Gram-Schmidt kernels: one round of loads per lane
-// (RPP * 16 rows) unless n needs more than 1024 such blocks
+// (RPP * 8 rows) unless n needs more than 1024 such blocks.  (RPP * 16 rows
+// per block, half the blocks with twice the loads in flight per lane, held
+// 233 registers against about half that and ran the unpreconditioned step
+// 54.3 us against 48.0 at n = 2^18, the network step 153.9 against 152.2.)
 static int64_t cgs_rpb(int64_t n) {
-    int64_t rpb = RPP * 16;
+    int64_t rpb = RPP * 8;
     while ((n + rpb - 1) / rpb > 1024) rpb *= 2;
     return rpb;
 }
