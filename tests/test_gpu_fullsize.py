@@ -137,6 +137,33 @@ def test_c2_first_cycle_gnp_f64(api, c2):
     assert abs(true - r["info"]["rel_res_true"]) <= 1e-8 * r["info"]["rel_res_true"]
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gram_schmidt_several_rounds_per_lane(api, prec):
+    """An 80^3 system (n = 512000): the Gram-Schmidt kernels take 512 rows per
+    block there (at most 1024 blocks), two rounds of loads per lane, where the
+    64^3 system takes one.  One unpreconditioned restart cycle against the
+    oracle's CGS2 residual history (FP64 1e-8, as the first cycle at 64^3; FP32
+    1e-3), and the true residual of x."""
+    import torch
+    A = I.convdiff3d(80, 10.0)
+    assert A.n == 512000
+    S = api.System(A)
+    ref = O.System(A)
+    b = A.to_scipy() @ np.ones(A.n) / S.gamma_input
+    x, info, hist = api.fgmres_solve(S, _dev(b, torch.float64), None, m=30, rtol=1e-12,
+                                     maxiters=30, prec=prec)
+    r = O.fgmres(ref, b, 30, 1e-12, 30, ortho=O.CGS2)
+    assert info["iters"] == r["info"]["iters"] == 30
+    rel = np.max(np.abs(hist - r["hist"]) / r["hist"])
+    print(f"{prec}: max relative difference of the residual estimates {rel:.2e}")
+    assert rel < (1e-8 if prec == "f64" else 1e-3)
+    xs = x.cpu().numpy()
+    true = np.linalg.norm(b - ref.A.to_scipy() @ xs) / np.linalg.norm(b)
+    assert abs(true - r["info"]["rel_res_true"]) <= (1e-8 if prec == "f64" else 1e-3) * \
+        r["info"]["rel_res_true"]
+
+
 def test_c2_batched_cycle_equals_single_solves(api, c2):
     """32 right-hand sides in lockstep for one restart cycle: every member's
     solution and counts equal the single solve's, bit for bit."""
