@@ -92,6 +92,40 @@ def test_spmv(api, name, prec):
     assert _relerr(y, yr) < tol
 
 
+def _drop_rows(A, every):
+    """A with every `every`-th row emptied (the diagonal of the others kept)."""
+    from paper_2406_00809_amd.inputs import CSR
+    keep = np.ones(A.n, dtype=bool)
+    keep[::every] = False
+    lens = np.diff(A.rowptr) * keep
+    rp = np.zeros(A.n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(lens)
+    mask = np.repeat(keep, np.diff(A.rowptr))
+    return CSR(A.n, rp.astype(np.int32), A.colind[mask], A.val[mask], A.name + "_holes")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("name", ["powerlaw_200000", "powerlaw_holes_150000", "powerlaw_2e20"])
+def test_spmv_irregular_at_scale(api, name):
+    """Irregular rows (power-law lengths 3..64, random columns) at 1.5e5 to
+    2^20 rows: the float32 product against the oracle's FP64 one, rows that
+    are empty (every 7th) and rows longer than one batch of a lane's entries
+    included, deterministic over calls."""
+    A = {"powerlaw_200000": lambda: I.powerlaw_random(200000, seed_structure=31, seed_values=32),
+         "powerlaw_holes_150000": lambda: _drop_rows(
+             I.powerlaw_random(150000, seed_structure=33, seed_values=34), 7),
+         "powerlaw_2e20": lambda: I.powerlaw_random(1 << 20, seed_structure=3, seed_values=4)}[name]()
+    S = api.System(A)
+    x = np.random.default_rng(35).standard_normal(A.n)
+    xd = _dev(x, _kdt("f32"))
+    y = S.spmv(xd, prec="f32").cpu().numpy()
+    yr = O.spmm(O.System(A).A, x)
+    assert _relerr(y, yr) < 2e-6
+    if "holes" in name:
+        assert np.all(y[::7] == 0.0)
+    np.testing.assert_array_equal(S.spmv(xd, prec="f32").cpu().numpy(), y)
+
+
 CASES = {
     # name: (matrix, L, d, h)
     "c1_laplace2d_32": (lambda: I.laplace2d(32), 4, 16, 32),
