@@ -791,21 +791,6 @@ __device__ __forceinline__ void layer_tiles_bf16(
     __shared__ __attribute__((aligned(16))) float sC3[DEC ? H : 4], sW4[DEC ? H : 4];
     const int lane = threadIdx.x % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(wcat);
-        for (int e = threadIdx.x; e < KB * NT * WAVE; e += BLOCK)
-            reinterpret_cast<uint4 *>(sW)[e] = src[e];
-        if constexpr (DEC) {
-            const uint4 *src3 = reinterpret_cast<const uint4 *>(w3);
-            for (int e = threadIdx.x; e < NW3; e += BLOCK) reinterpret_cast<uint4 *>(sW3)[e] = src3[e];
-            for (int e = threadIdx.x; e < H; e += BLOCK) {
-                sC3[e] = vec[oc3 + e];
-                sW4[e] = vec[oW4 + e];
-            }
-        }
-        __syncthreads();
-    }
-    if (skipped) return;
     const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv, B1);
     const int64_t ntiles = walk.end, nw = walk.stride;
     const uint32_t rowbytes = (uint32_t)B * (uint32_t)(D * sizeof(G));
@@ -830,6 +815,24 @@ __device__ __forceinline__ void layer_tiles_bf16(
         node_range(t, ifirst, nn);
         return rp[ifirst + (uint32_t)(lane <= nn ? lane : nn)];
     };
+    // the row pointers of the wavefront's first two tiles go out before the
+    // weights are staged, so that the two round trips overlap
+    const int32_t rp_first = fetch_rp(walk.t), rp_second = fetch_rp(walk.t + nw);
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(wcat);
+        for (int e = threadIdx.x; e < KB * NT * WAVE; e += BLOCK)
+            reinterpret_cast<uint4 *>(sW)[e] = src[e];
+        if constexpr (DEC) {
+            const uint4 *src3 = reinterpret_cast<const uint4 *>(w3);
+            for (int e = threadIdx.x; e < NW3; e += BLOCK) reinterpret_cast<uint4 *>(sW3)[e] = src3[e];
+            for (int e = threadIdx.x; e < H; e += BLOCK) {
+                sC3[e] = vec[oc3 + e];
+                sW4[e] = vec[oW4 + e];
+            }
+        }
+        __syncthreads();
+    }
+    if (skipped) return;
     // colind / value slice of tile t (rowptr slice rpv) into registers; lanes
     // past the slice re-read its last entry (an empty slice reads the entry
     // before it, or entry 0: nnz >= 1)
@@ -872,10 +875,10 @@ __device__ __forceinline__ void layer_tiles_bf16(
     // range known.  Everything loaded here is consumed here, so the loop
     // starts with no loads in flight.
     int64_t t = walk.t;
-    int32_t rp0 = fetch_rp(t);  // rowptr slice of the current tile
+    int32_t rp0 = rp_first;     // rowptr slice of the current tile
     int32_t kb0, cnt0;          // its entry range
     slice_range(t, rp0, kb0, cnt0);
-    int32_t rp1 = fetch_rp(t + nw);  // of the next tile
+    int32_t rp1 = rp_second;    // of the next tile
     {
         int32_t cv[NC];
         uint16_t av[NC];
@@ -1088,22 +1091,6 @@ __device__ __forceinline__ void layer_tiles_f32p(
     __shared__ __attribute__((aligned(16))) float sC3[DEC ? H : 4], sW4[DEC ? H : 4];
     const int lane = threadIdx.x % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    {
-        const float4 *src = reinterpret_cast<const float4 *>(wcat);
-        for (int e = threadIdx.x; e < KS * NT * WAVE / 4; e += BLOCK)
-            reinterpret_cast<float4 *>(sW)[e] = src[e];
-        if constexpr (DEC) {
-            const float4 *src3 = reinterpret_cast<const float4 *>(w3);
-            for (int e = threadIdx.x; e < NW3 / 4; e += BLOCK)
-                reinterpret_cast<float4 *>(sW3)[e] = src3[e];
-            for (int e = threadIdx.x; e < H; e += BLOCK) {
-                sC3[e] = vec[oc3 + e];
-                sW4[e] = vec[oW4 + e];
-            }
-        }
-        __syncthreads();
-    }
-    if (skipped) return;
     const TileWalk walk = xcd_walk((rows + 15) / 16, BLOCK / WAVE, wv, B1);
     const int64_t ntiles = walk.end, nw = walk.stride;
     const uint32_t rowbytes = (uint32_t)B * (uint32_t)(D * sizeof(G));
@@ -1124,6 +1111,25 @@ __device__ __forceinline__ void layer_tiles_f32p(
         node_range(t, ifirst, nn);
         return rp[ifirst + (uint32_t)(lane <= nn ? lane : nn)];
     };
+    // the row pointers of the wavefront's first two tiles go out before the
+    // weights are staged, so that the two round trips overlap
+    const int32_t rp_first = fetch_rp(walk.t), rp_second = fetch_rp(walk.t + nw);
+    {
+        const float4 *src = reinterpret_cast<const float4 *>(wcat);
+        for (int e = threadIdx.x; e < KS * NT * WAVE / 4; e += BLOCK)
+            reinterpret_cast<float4 *>(sW)[e] = src[e];
+        if constexpr (DEC) {
+            const float4 *src3 = reinterpret_cast<const float4 *>(w3);
+            for (int e = threadIdx.x; e < NW3 / 4; e += BLOCK)
+                reinterpret_cast<float4 *>(sW3)[e] = src3[e];
+            for (int e = threadIdx.x; e < H; e += BLOCK) {
+                sC3[e] = vec[oc3 + e];
+                sW4[e] = vec[oW4 + e];
+            }
+        }
+        __syncthreads();
+    }
+    if (skipped) return;
     auto slice_range = [&](int64_t t, int32_t rpv, int32_t &kbeg, int32_t &cnt) {
         uint32_t ifirst;
         int nn;
@@ -1154,10 +1160,10 @@ __device__ __forceinline__ void layer_tiles_f32p(
     };
 
     int64_t t = walk.t;
-    int32_t rp0 = fetch_rp(t);
+    int32_t rp0 = rp_first;
     int32_t kb0, cnt0;
     slice_range(t, rp0, kb0, cnt0);
-    int32_t rp1 = fetch_rp(t + nw);
+    int32_t rp1 = rp_second;
     {
         int32_t cv[NC];
         float av[NC];
