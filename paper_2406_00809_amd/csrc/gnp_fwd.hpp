@@ -280,7 +280,6 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
     const int64_t ntiles = (rows + 15) / 16, nw = (int64_t)gridDim.x * (BLOCK / WAVE);
     int64_t t = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
     IN vn = v[t * 16 + lane % 16 < rows ? t * 16 + lane % 16 : rows - 1];
-    if (skipped) return;
     // with the correction: rows t*16 + 8 rho + lane/8 (rho = 0, 1), lane
     // q = lane % 8 holding basis columns 4q..4q+3 of its row and the row's w;
     // columns past j are masked below (they may hold an older cycle)
@@ -321,6 +320,9 @@ __global__ __launch_bounds__(BLOCK) void k_encoder_p(
             tau[2] = tv / sqn;
         }
     }
+    // the flag is tested once the first tile's loads (input, correction rows
+    // and coefficients, divisor) are in flight: all in range, unused if set
+    if (skipped) return;
     for (; t < ntiles; t += nw) {
         const int64_t ra = t * 16 + lane % 16;
         IN vc;
