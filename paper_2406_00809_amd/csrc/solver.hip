@@ -304,9 +304,10 @@ __global__ __launch_bounds__(BLOCK) void k_normalize(int64_t n, const ST *__rest
                                                      int use_beta, Bat bt) {
     const int bi = blockIdx.y;
     ctl += bi;
-    if (ctl->cycle_done) return;
+    const int done = ctl->cycle_done;  // tested with the divisor in hand
     src += bi * bt.vec;
     const double div = use_beta ? ctl->beta : ctl->hnext;
+    if (done) return;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * BLOCK)
         vcur[i * bt.vstep + bi] = (KT)((double)src[i] / div);
@@ -554,12 +555,15 @@ __global__ __launch_bounds__(BLOCK) void k_cgs(int64_t n, int64_t rpb, KT *__res
 __global__ __launch_bounds__(BLOCK) void k_fin_dots(int nblk, int j, const double *partial,
                                                     int pstride, double *hout, Ctl *ctl, Bat bt) {
     ctl += blockIdx.y;
-    if (ctl->cycle_done) return;
+    // the end-of-cycle flag is tested once the partials have been read (in
+    // range either way), so that the two loads share one round trip
+    const int done = ctl->cycle_done;
     const int k = blockIdx.x;
     partial += blockIdx.y * bt.part;
     hout += blockIdx.y * bt.small;
     __shared__ double sh[BLOCK / WAVE];
     const double s = sum_partials(nblk, partial + (k <= j ? k : pstride - 1), pstride, sh);
+    if (done) return;
     if (threadIdx.x == 0) {
         if (k <= j) hout[k] = s;
         else ctl->wnorm0 = sqrt(s);
@@ -574,9 +578,11 @@ __global__ __launch_bounds__(BLOCK) void k_fin_dots(int nblk, int j, const doubl
 // column j of H-bar = h1 + h2, Givens rotation, residual estimate,
 // end-of-cycle decision.  The third pass then only updates w.  Inputs are
 // staged in LDS by all threads, the sequential rotation runs in one thread.
+// done: the block's end-of-cycle flag, read by the caller and tested here
+// once the inputs are staged (nothing is written when it is set).
 __device__ void givens_step(int j, const double *h1, const double *h2, Ctl *ctl, double *H,
                             double *H0, double *cs, double *sn, double *g, double *hist,
-                            uint64_t *tstamp) {
+                            uint64_t *tstamp, int done) {
     __shared__ double res[MAXCOL + 1];
     __shared__ double col[MAXCOL], scs[MAXCOL], ssn[MAXCOL];
     __shared__ double gj_s;
@@ -588,6 +594,7 @@ __device__ void givens_step(int j, const double *h1, const double *h2, Ctl *ctl,
     if (threadIdx.x == 0) gj_s = g[j];
     for (int i = threadIdx.x; i <= j + 1; i += BLOCK) res[i] = h2[i];
     __syncthreads();
+    if (done) return;
     for (int i = threadIdx.x; i <= j; i += BLOCK) {
         col[i] = h1[i] + res[i];
         H0[(int64_t)i * m + j] = col[i];
@@ -660,8 +667,9 @@ __global__ __launch_bounds__(BLOCK) void k_fin_sums2(int nblk, int j, const doub
     partial += blockIdx.y * bt.part;
     h2 += blockIdx.y * bt.small;
     __shared__ double sh[BLOCK / WAVE];
-    if (ctl->cycle_done) return;
+    const int done = ctl->cycle_done;  // tested after the partials, as in k_fin_dots
     const double s = sum_partials(nblk, partial + (k <= j ? k : pstride - 1), pstride, sh);
+    if (done) return;
     if (threadIdx.x == 0) h2[k] = s;
 }
 
@@ -672,10 +680,9 @@ __global__ __launch_bounds__(BLOCK) void k_fin_givens(int j, const double *h1, c
                                                       double *hist, Bat bt, uint64_t *tstamp) {
     const int bi = blockIdx.y;
     ctl += bi;
-    if (ctl->cycle_done) return;
     givens_step(j, h1 + bi * bt.small, h2 + bi * bt.small, ctl, H + bi * bt.hess,
                 H0 + bi * bt.hess, cs + bi * bt.small, sn + bi * bt.small, g + bi * bt.small,
-                hist ? hist + bi * bt.hist : nullptr, tstamp);
+                hist ? hist + bi * bt.hist : nullptr, tstamp, ctl->cycle_done);
 }
 
 // y = R^{-1} g on the leading columns with nonzero pivots: the triangle and g
